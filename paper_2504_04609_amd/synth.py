@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs for the OTLM solver.
+
+This module only draws inputs: bin grids, squared-distance costs, Gaussian-peak
+dictionaries and perturbed target spectra.  It contains none of the solver's
+arithmetic (no Gibbs kernel, no scaling updates), so that the GPU path and the
+FP64 reference can both be fed from it without sharing any of the method.
+
+Workload recipes (readings of the problem statement, section "Optimal Transport
+Linear Models"; the dictionary/target construction mirrors the spectroscopy
+demonstration and the scaling-test appendix):
+
+* bins: ``x_i = (i + 1/2) / n`` on [0, 1];
+* cost: ``C_ij = (x_i - x_j)^2``;
+* dictionary column j: Gaussian with centre ``c_j ~ U[0.1, 0.9]`` and standard
+  deviation ``sigma_j ~ U[0.01, 0.05]``, truncated at ``|x - c_j| > 5 sigma_j``
+  and normalised to unit discrete mass;
+* target: every peak centre moved by one per-spectrum shift ``delta``, the
+  shifted truncated Gaussians renormalised to unit mass, mixed with weights
+  ``w_true ~ Exp(1)``, multiplied by a gain ``g`` and given ``|N(0, 1e-3)|``
+  noise per bin (so every bin is strictly positive).
+
+Every spectrum b of a workload draws from its own stream
+``PCG64(SeedSequence([seed, b]))`` so any single spectrum of a large batch can be
+regenerated on its own; the dictionary draws from ``SeedSequence([seed, DICT])``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+DICT_STREAM = 1 << 30
+
+
+def rng_for(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
+
+
+def grid(n: int) -> np.ndarray:
+    """Bin centres of an n-bin grid on [0, 1]."""
+    return (np.arange(n, dtype=np.float64) + 0.5) / n
+
+
+def sq_cost(x_src: np.ndarray, x_tgt: np.ndarray) -> np.ndarray:
+    """Squared-distance cost matrix, FP64, [len(x_src), len(x_tgt)]."""
+    return (x_src[:, None] - x_tgt[None, :]) ** 2
+
+
+def gaussian_peaks(x: np.ndarray, centres: np.ndarray, sigmas: np.ndarray,
+                   trunc: float = 5.0) -> np.ndarray:
+    """Unit-mass truncated Gaussian columns, [len(x), len(centres)], FP64."""
+    d = x[:, None] - centres[None, :]
+    g = np.exp(-0.5 * (d / sigmas[None, :]) ** 2)
+    g[np.abs(d) > trunc * sigmas[None, :]] = 0.0
+    mass = g.sum(axis=0, keepdims=True)
+    if np.any(mass <= 0):
+        raise ValueError("a peak has no support on the grid")
+    return g / mass
+
+
+@dataclasses.dataclass
+class Dictionary:
+    x: np.ndarray        # [n] bin centres
+    centres: np.ndarray  # [k]
+    sigmas: np.ndarray   # [k]
+    D: np.ndarray        # [n, k] FP64, unit-mass columns
+
+
+def make_dictionary(n: int, k: int, seed: int) -> Dictionary:
+    rng = rng_for(seed, DICT_STREAM)
+    x = grid(n)
+    c = rng.uniform(0.1, 0.9, k)
+    s = rng.uniform(0.01, 0.05, k)
+    return Dictionary(x, c, s, gaussian_peaks(x, c, s))
+
+
+def make_target(d: Dictionary, seed: int, b: int, shift: float,
+                gain: tuple[float, float], noise: float = 1e-3):
+    """One perturbed target spectrum; returns (y [n], w_true [k], delta, g)."""
+    rng = rng_for(seed, b)
+    k = d.centres.size
+    w_true = rng.exponential(1.0, k)
+    delta = rng.uniform(-shift, shift) if shift > 0 else 0.0
+    g = rng.uniform(gain[0], gain[1]) if gain[1] > gain[0] else gain[0]
+    eta = np.abs(rng.normal(0.0, noise, d.x.size))
+    y = g * (gaussian_peaks(d.x, d.centres + delta, d.sigmas) @ w_true) + eta
+    return y, w_true, delta, g
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: int
+    k: int
+    B: int
+    eps: float
+    fit: str            # 'kl' | 'tv' | 'l2' | 'l2tv' | 'balanced'
+    pen: str            # 'none' | 'l1' | 'l2sq' | 'en'
+    lam: float
+    alpha: float
+    lam2: float = 0.0
+    beta: float = 0.0
+    seed: int = 0
+    shift: float = 0.0
+    gain: tuple = (1.0, 1.0)
+    dict_seed: int | None = None
+
+    def dictionary(self) -> Dictionary:
+        return make_dictionary(self.n, self.k, self.seed if self.dict_seed is None else self.dict_seed)
+
+    def targets(self, idx=None, dic: Dictionary | None = None) -> np.ndarray:
+        """Targets [len(idx), n] FP64 (all B spectra when idx is None)."""
+        dic = dic or self.dictionary()
+        idx = range(self.B) if idx is None else idx
+        return np.stack([make_target(dic, self.seed, int(b), self.shift, self.gain)[0] for b in idx])
+
+    def cost(self) -> np.ndarray:
+        x = grid(self.n)
+        return sq_cost(x, x)
+
+
+# The five workloads.  Unstated parameters: KL weight lambda = 1 wherever the
+# datafit is KL; squared-l2 penalty is alpha/2 ||w||^2; l1 penalty is alpha ||w||_1.
+CONFIG1 = Workload("single_n200_k10", n=200, k=10, B=1, eps=0.01, fit="kl", pen="l2sq",
+                   lam=1.0, alpha=1e-3, seed=1, shift=0.02, gain=(1.0, 1.0))
+CONFIG2 = Workload("batch_n1024_k64_l1", n=1024, k=64, B=4096, eps=0.005, fit="kl", pen="l1",
+                   lam=1.0, alpha=1e-2, seed=2, shift=0.03, gain=(0.8, 1.2))
+CONFIG3 = dataclasses.replace(CONFIG2, name="batch_n1024_k64_l1_eps1e-3", eps=0.001)
+CONFIG5_EVAL = dataclasses.replace(CONFIG2, name="heldout_n1024_k64_l1_eps2e-3", eps=0.002,
+                                   seed=6, dict_seed=2)
+CONFIG5_TRAIN = dataclasses.replace(CONFIG5_EVAL, name="train_n1024_k64_l1_eps2e-3", B=200_000,
+                                    seed=5)
