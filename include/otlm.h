@@ -1,0 +1,177 @@
+/*
+ * libotlm -- batched entropic Optimal Transport Linear Model solver for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library solves, for many target spectra y_b at once, the regularised
+ * OTLM problem of Kacprzak et al., "Scalable Approximate Algorithms for
+ * Optimal Transport Linear Models" (eq. OTLM, in the scaling-algorithm form
+ * of section "Scaling Algorithm Framework for OTLM"):
+ *
+ *   min_{Q >= 0, w >= 0}  eps KL(Q || K) + lambda L(Q^T 1 | y) + alpha R(w)
+ *   subject to Q 1 = D w,           K = exp(-C / eps),
+ *
+ * with the scaling iteration of Algorithm 1: per iteration
+ *   s = K v;  w <- wMMstep(s, Z | D)  (Table 2 / Appendix A);  u = D w / s;
+ *   t = K^T u;  p = prox_L(t | y)      (Table 1);              v = p / t.
+ * The plan is Q = diag(u) K diag(v) (row i = source bin, column j = target).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers to contiguous row-major arrays,
+ *    owned by the caller; the library never frees them.  Batched arrays are
+ *    [B, n] (one spectrum per row) or [B, k].
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; a call returns once its work is enqueued, except
+ *    where a comment says it synchronises.
+ *  - Return value: OTLM_OK (0) or a negative otlm_status.  On a negative
+ *    return nothing has been written to the outputs unless stated.  Argument
+ *    errors are detected before any launch.
+ *  - Not thread-safe per kernel object: calls that share an otlm_kernel must
+ *    be serialised by the caller (they share its workspace).
+ */
+#ifndef OTLM_H
+#define OTLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct otlm_kernel_s* otlm_kernel;
+
+typedef enum {
+  OTLM_OK = 0,
+  OTLM_E_INVALID = -1,      /* bad argument (null pointer, size, parameter range) */
+  OTLM_E_HIP = -2,          /* a HIP runtime call failed                        */
+  OTLM_E_NOMEM = -3,        /* device allocation failed                         */
+  OTLM_E_UNSUPPORTED = -4   /* valid request this build does not implement      */
+} otlm_status;
+
+/* Target datafit L (Table 1).  L2_TV is lambda * L2 + lambda2 * TV with
+ * prox_{L2} o prox_{TV}; POISSON is the negative Poisson log-likelihood with
+ * the reciprocal reading 1 / W_0 of the table's last row. */
+typedef enum {
+  OTLM_FIT_BALANCED = 0, OTLM_FIT_KL = 1, OTLM_FIT_TV = 2, OTLM_FIT_L2 = 3,
+  OTLM_FIT_L2_TV = 4, OTLM_FIT_POISSON = 5
+} otlm_datafit;
+
+/* Weight penalty alpha R(w) (Table 2, Appendix A): none; alpha ||w||_1;
+ * (alpha/2) ||w||_2^2; alpha ||w||_1 + (beta/2) ||w||_2^2. */
+typedef enum {
+  OTLM_PEN_NONE = 0, OTLM_PEN_L1 = 1, OTLM_PEN_L2SQ = 2, OTLM_PEN_ELASTIC = 3
+} otlm_penalty;
+
+typedef enum {
+  OTLM_PREC_FP32 = 0,          /* FP32 kernel products on MFMA, FP32 updates */
+  OTLM_PREC_BF16_REFINE = 1    /* BF16 products (FP32 accumulate), then FP32 sweeps */
+} otlm_precision;
+
+/* Per-spectrum outcome flags written to status[b]. */
+enum {
+  OTLM_S_CONVERGED = 1,   /* weight change and source violation <= tol          */
+  OTLM_S_MAX_ITER = 2,    /* stopped at max_iter                                 */
+  OTLM_S_NONFINITE = 4    /* a NaN/Inf appeared; the spectrum was frozen         */
+};
+
+typedef struct {
+  double eps;            /* entropic regulariser, > 0 (must equal the kernel's)   */
+  double lambda;         /* datafit weight, >= 0                                   */
+  double lambda2;        /* TV weight of OTLM_FIT_L2_TV, >= 0                      */
+  double alpha;          /* penalty weight, >= 0 (> 0 for L2SQ)                    */
+  double beta;           /* quadratic weight of OTLM_PEN_ELASTIC, > 0 there        */
+  double tol;            /* stop a spectrum when max|dw|/max|w| <= tol and
+                            sum|u*(Kv) - Dw| / sum(Dw) <= tol; 0 = run max_iter   */
+  int32_t max_iter;      /* >= 1                                                   */
+  int32_t check_every;   /* convergence test cadence in iterations, >= 1           */
+  int32_t fit;           /* otlm_datafit                                           */
+  int32_t pen;           /* otlm_penalty                                           */
+  int32_t prec;          /* otlm_precision                                         */
+  int32_t warm;          /* 0: cold start (w0_j = sum(y)/(k x_j), v = 1);
+                            1: start from the W and logV arrays passed in          */
+  int32_t refine_sweeps; /* FP32 sweeps after the BF16 phase (BF16_REFINE)         */
+  int32_t reserved;
+} otlm_params;
+
+/* Fill `p` with defaults: KL datafit, no penalty, eps = lambda = 1, tol 1e-6,
+ * max_iter 1000, check_every 10, FP32, cold start. */
+void otlm_default_params(otlm_params* p);
+
+/* Build the Gibbs kernel K = exp(-C / eps) (Algorithm 1, initialisation).
+ *   C       device, FP64, [n, n] row-major cost (row = source bin i, column =
+ *           target bin j); read only during the call.  The OTLM problem has
+ *           the same bins on both sides, so C is square.
+ *   n       number of bins, 1 <= n <= 16384.
+ *   eps     > 0.
+ *   out     receives an opaque handle owning device copies of K (FP32 and
+ *           BF16), K^T when C is not symmetric, and sum(K) in FP64.
+ * Synchronises `stream` (it checks C for symmetry on the host).
+ * Errors: OTLM_E_INVALID (null, n out of range, eps <= 0), OTLM_E_NOMEM,
+ * OTLM_E_HIP. */
+int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_kernel* out);
+
+/* Release a kernel object and every workspace it cached.  NULL is a no-op.
+ * Synchronises the device. */
+int otlm_free_kernel(otlm_kernel k);
+
+/* Number of bins and symmetry flag of a kernel object. */
+int otlm_kernel_info(otlm_kernel k, int64_t* n, int32_t* symmetric, double* eps);
+
+/* Run Algorithm 1 on B target spectra that share K and the dictionary D.
+ *   D       device FP32 [n, kdim], non-negative, every column sum > 0 (the
+ *           paper's X; column sums are the x_j of Table 2's caption).
+ *   Y       device FP32 [B, n], non-negative targets.
+ *   W       device FP32 [B, kdim]: output weights; read as the start when
+ *           p->warm == 1.
+ *   logU    device FP32 [B, n] or NULL: output log of the source scaling u.
+ *   logV    device FP32 [B, n]: output log of the target scaling v; read as
+ *           the start when p->warm == 1.
+ *   iters   device int32 [B] or NULL: iteration at which each spectrum
+ *           stopped (a multiple of check_every, or max_iter).
+ *   status  device int32 [B] or NULL: OTLM_S_* flags.
+ * Each spectrum is frozen once its own test passes, so its result does not
+ * depend on the other spectra of the batch.  The host thread blocks once per
+ * `check_every` iterations to read the number of active spectra.
+ * Errors: OTLM_E_INVALID (bad sizes or parameters: eps must equal the
+ * kernel's, 1 <= kdim <= 256, B >= 0), OTLM_E_UNSUPPORTED, OTLM_E_NOMEM,
+ * OTLM_E_HIP.  B = 0 is a no-op. */
+int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y, int64_t B,
+                     const otlm_params* p, float* W, float* logU, float* logV,
+                     int32_t* iters, int32_t* status, void* stream);
+
+/* FP64 objective and optimality residuals at (W, logU, logV), per spectrum
+ * (eq. OTLM in the scaling form eps KL(Q||K) + F1(Q1) + F2(Q^T 1) and its
+ * Fenchel dual).  out is device FP64 [B, 6]:
+ *   [0] primal  eps KL(Q||K) + lambda L(Q^T 1|y) + alpha R(w),  Q = diag(u) K diag(v)
+ *   [1] dual    -F1*(-f) - F2*(-g) - eps sum_ij K_ij (e^{(f_i+g_j)/eps} - 1),
+ *               f = eps log u, g = eps log v  (NaN for POISSON and BALANCED; for
+ *               L1 / NONE the indicator F1* counts as 0 and feasibility
+ *               D^T f >= -alpha shows in [5])
+ *   [2] <C, Q>  transport cost (needs C: pass the same C as to make_kernel)
+ *   [3] ||Q1 - Dw||_1 / ||Dw||_1
+ *   [4] max_j dist(-g_j, dF2(m_j)) / lambda,  m = Q^T 1
+ *   [5] max_j |min(w_j, alpha R'(w_j) + eps (D^T log u)_j)|
+ * C is device FP64 [n, n].  Errors as otlm_solve_batch. */
+int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim, const float* Y,
+                   int64_t B, const otlm_params* p, const float* W, const float* logU,
+                   const float* logV, double* out, void* stream);
+
+/* Kernel timing on the solve's own stream.  While enabled, otlm_solve_batch
+ * brackets every launch of its hot kernels with HIP events and accumulates
+ * their durations per kernel class:
+ *   [0] s = K v product (+ log-ratio epilogue)   [1] weight step (R D + MM map)
+ *   [2] a = D w, u = a / s                        [3] t = K^T u product (+ prox)
+ *   [4] convergence test
+ * otlm_profile_read copies the mean duration in ms per launch (ms[5]) and the
+ * launch counts (count[5]) accumulated since the last enable, synchronising
+ * the recorded events first.  Enabling resets the counters.  Errors:
+ * OTLM_E_INVALID for a null kernel. */
+int otlm_profile_enable(otlm_kernel k, int32_t on);
+int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count);
+
+/* Static description of an otlm_status code. */
+const char* otlm_status_str(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTLM_H */

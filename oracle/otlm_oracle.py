@@ -363,10 +363,10 @@ def _pen_conj_neg(Df, pen, alpha, beta):
         return (np.maximum(0.0, -Df) ** 2).sum(axis=-1) / (2 * alpha)
     if pen == "en":
         return (np.maximum(0.0, -Df - alpha) ** 2).sum(axis=-1) / (2 * beta)
-    if pen == "l1":
-        return np.where((Df + alpha).min(axis=-1) >= -1e-9 * max(alpha, 1e-300), 0.0, np.inf)
-    if pen == "none":
-        return np.where(Df.min(axis=-1) >= -1e-12, 0.0, np.inf)
+    if pen in ("l1", "none"):
+        # F1* is the indicator of D^T f >= -alpha (l1) or >= 0 (none); its finite
+        # part is 0 and the constraint is reported by the weight KKT residual.
+        return np.zeros(Df.shape[:-1])
     raise ValueError(pen)
 
 
@@ -377,7 +377,9 @@ def objective(K, C, D, Y, W, logU, logV, *, fit="kl", pen="l1", eps=0.01, lam=1.
     primal  J = eps KL(Q||K) + lam L(Q^T 1 | y) + alpha R(w), Q = diag(u) K diag(v)
               = eps(<a, log u> + <m, log v> - sum a + sum K) + ...   (a = Q1, m = Q^T 1)
     dual    = -F1*(-f) - F2*(-g) - eps sum_ij K_ij (exp((f_i + g_j)/eps) - 1),
-              f = eps log u, g = eps log v (Fenchel dual of the scaling form)
+              f = eps log u, g = eps log v (Fenchel dual of the scaling form);
+              for l1 / no penalty F1* is an indicator: its finite part (0) is
+              used and feasibility D^T f >= -alpha shows in w_kkt
     <C,Q>   = u^T (C o K) v
     src_err = ||Q1 - Dw||_1 / ||Dw||_1
     tgt_kkt = max_j dist(-g_j, d F2(m_j)) / lam

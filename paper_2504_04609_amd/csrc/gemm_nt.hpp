@@ -1,0 +1,186 @@
+// FP32 "NT" GEMM on CDNA4 matrix cores with a fused, per-element epilogue.
+//
+//   C[m, n] = sum_k A[m, k] * Bt[n, k]        (A: [M, Kd], Bt: [N, Kd], both row-major)
+//
+// Both operands are read along k, which is the layout every product of the
+// scaling loop needs without a transpose: S = V K^T reads K itself, T = U K
+// reads K^T (the same array when the cost is symmetric), the dictionary
+// products read D or D^T.
+//
+// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) owns a BM x BN
+// output tile; each wave owns (BM/2) x (BN/2) as 32 x 32 fragments of
+// v_mfma_f32_32x32x2_f32.  k advances in stages of 16; each stage is staged in
+// LDS with rows padded to 20 floats so that the 128-bit LDS reads of a
+// half-wave hit distinct banks, and the next stage is prefetched into registers
+// while the current one is multiplied (one barrier per stage).  Inside a stage
+// the lanes of half h supply k = 8h .. 8h+7, so each lane reads its operands
+// with two 128-bit LDS loads; the k order only permutes the sum.
+//
+// Requirements (checked by the host): lda, ldb multiples of 4, 16-byte aligned
+// base pointers, Kd a multiple of 16 (operands are zero-padded), M, N >= 1.
+// Rows of A beyond M and rows of Bt beyond N are read as zero.
+//
+// Epilogue contract (Epi):
+//   static constexpr int NRED;                 // 0..2 row reductions
+//   static constexpr bool RED_IS_MAX[2];      // max (true) or sum (false)
+//   bool do_red;                               // runtime switch for the reductions
+//   __device__ void elem(int m, int n, float c, float* red) const;
+//   __device__ void row_partial(int m, int tile, const float* red) const;
+// elem() is called once for every (m < M, n < N); row_partial() once per row
+// m < M of the tile with the reductions over the tile's columns.
+#pragma once
+#include <hip/hip_runtime.h>
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int GEMM_BK = 16;
+constexpr int GEMM_LDS_LD = 20;
+
+struct GemmArgs {
+  const float* A;
+  int lda;
+  const float* Bt;
+  int ldb;
+  int M, N, Kd;
+};
+
+template <bool IS_MAX>
+__device__ __forceinline__ float red_op(float a, float b) {
+  return IS_MAX ? fmaxf(a, b) : a + b;
+}
+
+template <bool IS_MAX>
+__device__ __forceinline__ float half_wave_reduce(float v) {
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) v = red_op<IS_MAX>(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <int BM, int BN, class Epi>
+__global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
+  constexpr int BK = GEMM_BK, LD = GEMM_LDS_LD;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
+  constexpr int A_V4 = BM * (BK / 4) / 256;
+  constexpr int B_V4 = BN * (BK / 4) / 256;
+  static_assert(FM >= 1 && FN >= 1 && A_V4 >= 1 && B_V4 >= 1, "tile too small");
+
+  __shared__ __attribute__((aligned(16))) float As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+
+  f32x4 ra[A_V4], rb[B_V4];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int q = 0; q < A_V4; ++q) {
+      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = m0 + r;
+      ra[q] = gr < g.M ? *reinterpret_cast<const f32x4*>(g.A + (size_t)gr * g.lda + kt * BK + c)
+                       : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int q = 0; q < B_V4; ++q) {
+      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = n0 + r;
+      rb[q] = gr < g.N ? *reinterpret_cast<const f32x4*>(g.Bt + (size_t)gr * g.ldb + kt * BK + c)
+                       : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < A_V4; ++q) {
+      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
+      *reinterpret_cast<f32x4*>(&As[buf][r * LD + c]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B_V4; ++q) {
+      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
+      *reinterpret_cast<f32x4*>(&Bs[buf][r * LD + c]) = rb[q];
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int nk = g.Kd / BK;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    f32x4 a[FM][2], b[FN][2];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const float* pa = &As[cur][(wm * WM + fm * 32 + l32) * LD + h * 8];
+      a[fm][0] = *reinterpret_cast<const f32x4*>(pa);
+      a[fm][1] = *reinterpret_cast<const f32x4*>(pa + 4);
+    }
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      const float* pb = &Bs[cur][(wn * WN + fn * 32 + l32) * LD + h * 8];
+      b[fn][0] = *reinterpret_cast<const f32x4*>(pb);
+      b[fn][1] = *reinterpret_cast<const f32x4*>(pb + 4);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[fm][p >> 2][p & 3], b[fn][p >> 2][p & 3],
+                                                              acc[fm][fn], 0, 0, 0);
+    if (kt + 1 < nk) swrite(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue.  32x32 accumulator layout: lane l, register r holds
+  // row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of its fragment.
+  __shared__ float red_s[2][BM][2];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wm * WM + fm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      const int m = m0 + row;
+      float red[2] = {Epi::RED_IS_MAX[0] ? 0.f : 0.f, 0.f};
+      if (m < g.M) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const int n = n0 + wn * WN + fn * 32 + l32;
+          if (n < g.N) epi.elem(m, n, acc[fm][fn][r], red);
+        }
+      }
+      if constexpr (Epi::NRED > 0) {
+        if (epi.do_red) {
+          red[0] = half_wave_reduce<Epi::RED_IS_MAX[0]>(red[0]);
+          if constexpr (Epi::NRED > 1) red[1] = half_wave_reduce<Epi::RED_IS_MAX[1]>(red[1]);
+          if (l32 == 0) {
+            red_s[wn][row][0] = red[0];
+            red_s[wn][row][1] = red[1];
+          }
+        }
+      }
+    }
+  }
+  if constexpr (Epi::NRED > 0) {
+    if (epi.do_red) {
+      __syncthreads();
+      for (int row = tid; row < BM; row += 256) {
+        const int m = m0 + row;
+        if (m < g.M) {
+          float v[2];
+          v[0] = red_op<Epi::RED_IS_MAX[0]>(red_s[0][row][0], red_s[1][row][0]);
+          v[1] = red_op<Epi::RED_IS_MAX[1]>(red_s[0][row][1], red_s[1][row][1]);
+          epi.row_partial(m, blockIdx.x, v);
+        }
+      }
+    }
+  }
+}

@@ -1,0 +1,476 @@
+// libotlm: C-ABI and host engine of the batched OTLM scaling solver (gfx950).
+//
+// One call of otlm_solve_batch runs Algorithm 1 ("Scaling Algorithm for OTLM")
+// for B spectra that share the Gibbs kernel K and the dictionary D.  Per
+// iteration it issues four MFMA GEMM launches, each with the elementwise
+// update of that step fused into its epilogue:
+//   1. S = V K^T      -> s, r = log(s / a)              (kernel product, Table 2 input)
+//   2. G = R D        -> w = wMMstep(...)                (Table 2 / Appendix A)
+//   3. A = W D^T      -> a = D w, u = a / s              (source scaling)
+//   4. T = U K        -> v = prox_L(t | y) / t           (Table 1, target scaling)
+// and, every check_every iterations, one convergence kernel whose active-count
+// is the only value read back by the host inside the loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/otlm.h"
+#include "gemm_nt.hpp"
+#include "objective_kernels.hpp"
+#include "solver_kernels.hpp"
+
+namespace {
+
+#define OTLM_HIP(call)                                      \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) {                                 \
+      std::fprintf(stderr, "libotlm: %s failed: %s (%s:%d)\n", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return OTLM_E_HIP;                                    \
+    }                                                       \
+  } while (0)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Workspace {
+  int64_t B = 0, np = 0, kp = 0;
+  float *V = nullptr, *S = nullptr, *R = nullptr, *A = nullptr, *U = nullptr, *W = nullptr;
+  float *Dp = nullptr, *DTp = nullptr;
+  float4* colc = nullptr;
+  float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr;
+  int *done = nullptr, *iters = nullptr, *status = nullptr, *flags = nullptr;
+  float* ew_prev = nullptr;
+  double *os = nullptr, *ot = nullptr, *oq = nullptr;
+  int64_t obj_B = 0;
+  int* host_flags = nullptr;  // pinned: [0] active count, [1] bad-input flag
+  std::vector<void*> allocs;
+
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    if (host_flags) (void)hipHostFree(host_flags);
+    host_flags = nullptr;
+    B = np = kp = 0;
+    V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = nullptr;
+    colc = nullptr;
+    done = iters = status = flags = nullptr;
+    ew_prev = nullptr;
+  }
+  void release_obj() {
+    if (os) (void)hipFree(os);
+    if (ot) (void)hipFree(ot);
+    if (oq) (void)hipFree(oq);
+    os = ot = oq = nullptr;
+    obj_B = 0;
+  }
+};
+
+constexpr float OTLM_FP32_FLOOR = 4.76837158e-7f;  // 2^-21: weight changes below it are FP32 noise
+constexpr int MAX_TILES = 256;  // per-row partial slots: np / 64 <= 256 column tiles
+
+}  // namespace
+
+struct otlm_kernel_s {
+  int device = 0;
+  int64_t n = 0, np = 0;
+  double eps = 0.0;
+  int symmetric = 0;
+  float* K = nullptr;     // [np, np] FP32, zero padded
+  float* KT = nullptr;    // == K when symmetric
+  double* K64 = nullptr;  // [n, n] FP64
+  double* KT64 = nullptr; // == K64 when symmetric
+  double sumK = 0.0;
+  Workspace ws;
+  // kernel timing (otlm_profile_*)
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+template <class T>
+int dev_alloc(Workspace& ws, T** p, size_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return OTLM_E_NOMEM;
+  ws.allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return OTLM_OK;
+}
+
+int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
+  Workspace& ws = k->ws;
+  if (ws.B >= B && ws.kp >= kp && ws.np == k->np && ws.host_flags) return OTLM_OK;
+  ws.release();
+  const int64_t np = k->np;
+  const size_t bn = (size_t)B * np, bk = (size_t)B * kp;
+  int rc = OTLM_OK;
+  rc |= dev_alloc(ws, &ws.V, bn);
+  rc |= dev_alloc(ws, &ws.S, bn);
+  rc |= dev_alloc(ws, &ws.R, bn);
+  rc |= dev_alloc(ws, &ws.A, bn);
+  rc |= dev_alloc(ws, &ws.U, bn);
+  rc |= dev_alloc(ws, &ws.W, bk);
+  rc |= dev_alloc(ws, &ws.Dp, (size_t)np * kp);
+  rc |= dev_alloc(ws, &ws.DTp, (size_t)kp * np);
+  rc |= dev_alloc(ws, &ws.colc, (size_t)kp);
+  rc |= dev_alloc(ws, &ws.psn, (size_t)B * MAX_TILES);
+  rc |= dev_alloc(ws, &ws.psd, (size_t)B * MAX_TILES);
+  rc |= dev_alloc(ws, &ws.pwn, (size_t)B * MAX_TILES);
+  rc |= dev_alloc(ws, &ws.pwd, (size_t)B * MAX_TILES);
+  rc |= dev_alloc(ws, &ws.done, (size_t)B);
+  rc |= dev_alloc(ws, &ws.iters, (size_t)B);
+  rc |= dev_alloc(ws, &ws.status, (size_t)B);
+  rc |= dev_alloc(ws, &ws.flags, 4);
+  rc |= dev_alloc(ws, &ws.ew_prev, (size_t)B);
+  if (rc != OTLM_OK) {
+    ws.release();
+    return OTLM_E_NOMEM;
+  }
+  if (hipHostMalloc((void**)&ws.host_flags, 4 * sizeof(int)) != hipSuccess) {
+    ws.release();
+    return OTLM_E_NOMEM;
+  }
+  ws.B = B;
+  ws.np = np;
+  ws.kp = kp;
+  return OTLM_OK;
+}
+
+// Tile shapes of the four products (chosen per problem size).
+template <class Epi>
+void gemm(int bm, int bn, const GemmArgs& g, const Epi& e, hipStream_t s) {
+  auto launch = [&](auto kern, int BM, int BN) {
+    dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g, e);
+  };
+  if (bm == 128 && bn == 128) launch(gemm_nt_f32<128, 128, Epi>, 128, 128);
+  else if (bm == 128 && bn == 64) launch(gemm_nt_f32<128, 64, Epi>, 128, 64);
+  else if (bm == 64 && bn == 128) launch(gemm_nt_f32<64, 128, Epi>, 64, 128);
+  else launch(gemm_nt_f32<64, 64, Epi>, 64, 64);
+}
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  otlm_kernel k;
+  int cls;
+  hipStream_t s;
+  std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+  ProfScope(otlm_kernel k_, int cls_, hipStream_t s_) : k(k_), cls(cls_), s(s_) {
+    if (!k->profile) return;
+    if (!k->ev_pool.empty()) {
+      e = k->ev_pool.back();
+      k->ev_pool.pop_back();
+    } else if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) {
+      e = {nullptr, nullptr};
+      return;
+    }
+    (void)hipEventRecord(e.first, s);
+  }
+  ~ProfScope() {
+    if (!e.first) return;
+    (void)hipEventRecord(e.second, s);
+    k->ev[cls].push_back(e);
+  }
+};
+
+// Fold recorded event pairs into the running means (synchronises the events).
+void prof_collect(otlm_kernel k) {
+  for (int c = 0; c < 5; ++c) {
+    for (auto& e : k->ev[c]) {
+      float ms = 0.f;
+      if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+        k->prof_ms[c] += ms;
+        k->prof_n[c] += 1;
+      }
+      k->ev_pool.push_back(e);
+    }
+    k->ev[c].clear();
+  }
+}
+
+bool params_valid(const otlm_params* p, double kernel_eps) {
+  if (!p) return false;
+  if (!(p->eps > 0.0) || std::fabs(p->eps - kernel_eps) > 1e-12 * kernel_eps) return false;
+  if (!(p->lambda >= 0.0) || !(p->lambda2 >= 0.0) || !(p->alpha >= 0.0) || !(p->beta >= 0.0)) return false;
+  if (!(p->tol >= 0.0) || p->max_iter < 1 || p->check_every < 1) return false;
+  if (p->fit < OTLM_FIT_BALANCED || p->fit > OTLM_FIT_POISSON) return false;
+  if (p->pen < OTLM_PEN_NONE || p->pen > OTLM_PEN_ELASTIC) return false;
+  if (p->pen == OTLM_PEN_L2SQ && !(p->alpha > 0.0)) return false;
+  if (p->pen == OTLM_PEN_ELASTIC && !(p->beta > 0.0)) return false;
+  if ((p->fit == OTLM_FIT_L2 || p->fit == OTLM_FIT_L2_TV || p->fit == OTLM_FIT_POISSON) && !(p->lambda > 0.0))
+    return false;
+  if (p->warm != 0 && p->warm != 1) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void otlm_default_params(otlm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->eps = 1.0;
+  p->lambda = 1.0;
+  p->tol = 1e-6;
+  p->max_iter = 1000;
+  p->check_every = 10;
+  p->fit = OTLM_FIT_KL;
+  p->pen = OTLM_PEN_NONE;
+  p->prec = OTLM_PREC_FP32;
+}
+
+const char* otlm_status_str(int code) {
+  switch (code) {
+    case OTLM_OK: return "ok";
+    case OTLM_E_INVALID: return "invalid argument";
+    case OTLM_E_HIP: return "HIP runtime error";
+    case OTLM_E_NOMEM: return "out of device memory";
+    case OTLM_E_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_kernel* out) {
+  if (!C || !out || n < 1 || n > 16384 || !(eps > 0.0) || !std::isfinite(eps)) return OTLM_E_INVALID;
+  *out = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* k = new (std::nothrow) otlm_kernel_s();
+  if (!k) return OTLM_E_NOMEM;
+  OTLM_HIP(hipGetDevice(&k->device));
+  k->n = n;
+  k->np = round_up(n, 64);
+  k->eps = eps;
+  // symmetry test on the host (C is read once at set-up)
+  std::vector<double> hc((size_t)n * n);
+  if (hipMemcpyAsync(hc.data(), C, hc.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    delete k;
+    return OTLM_E_HIP;
+  }
+  bool sym = true, finite = true;
+  for (int64_t i = 0; i < n && finite; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double c = hc[(size_t)i * n + j];
+      if (std::isnan(c) || c == -INFINITY) { finite = false; break; }
+      if (j > i && c != hc[(size_t)j * n + i]) sym = false;
+    }
+  if (!finite) {
+    delete k;
+    return OTLM_E_INVALID;
+  }
+  k->symmetric = sym ? 1 : 0;
+  const size_t npp = (size_t)k->np * k->np;
+  if (hipMalloc(&k->K, npp * sizeof(float)) != hipSuccess ||
+      hipMalloc(&k->K64, (size_t)n * n * sizeof(double)) != hipSuccess) {
+    otlm_free_kernel(k);
+    return OTLM_E_NOMEM;
+  }
+  if (sym) {
+    k->KT = k->K;
+    k->KT64 = k->K64;
+  } else if (hipMalloc(&k->KT, npp * sizeof(float)) != hipSuccess ||
+             hipMalloc(&k->KT64, (size_t)n * n * sizeof(double)) != hipSuccess) {
+    otlm_free_kernel(k);
+    return OTLM_E_NOMEM;
+  }
+  const double inv = 1.0 / eps;
+  dim3 g32((unsigned)((k->np + 255) / 256), (unsigned)k->np), g64((unsigned)((n + 255) / 256), (unsigned)n);
+  hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->K);
+  hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 0, k->K64);
+  if (!sym) {
+    hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KT);
+    hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 1, k->KT64);
+  }
+  if (hipGetLastError() != hipSuccess) {
+    otlm_free_kernel(k);
+    return OTLM_E_HIP;
+  }
+  double sum = 0.0;
+  for (size_t i = 0; i < hc.size(); ++i) sum += std::exp(-hc[i] * inv);
+  k->sumK = sum;
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    otlm_free_kernel(k);
+    return OTLM_E_HIP;
+  }
+  *out = k;
+  return OTLM_OK;
+}
+
+int otlm_profile_enable(otlm_kernel k, int32_t on) {
+  if (!k) return OTLM_E_INVALID;
+  prof_collect(k);
+  for (int c = 0; c < 5; ++c) {
+    k->prof_ms[c] = 0.0;
+    k->prof_n[c] = 0;
+  }
+  k->profile = on != 0;
+  return OTLM_OK;
+}
+
+int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count) {
+  if (!k) return OTLM_E_INVALID;
+  prof_collect(k);
+  for (int c = 0; c < 5; ++c) {
+    if (ms) ms[c] = k->prof_n[c] ? k->prof_ms[c] / (double)k->prof_n[c] : 0.0;
+    if (count) count[c] = k->prof_n[c];
+  }
+  return OTLM_OK;
+}
+
+int otlm_free_kernel(otlm_kernel k) {
+  if (!k) return OTLM_OK;
+  (void)hipDeviceSynchronize();
+  prof_collect(k);
+  for (auto& e : k->ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  k->ws.release();
+  k->ws.release_obj();
+  if (k->KT && k->KT != k->K) (void)hipFree(k->KT);
+  if (k->K) (void)hipFree(k->K);
+  if (k->KT64 && k->KT64 != k->K64) (void)hipFree(k->KT64);
+  if (k->K64) (void)hipFree(k->K64);
+  delete k;
+  return OTLM_OK;
+}
+
+int otlm_kernel_info(otlm_kernel k, int64_t* n, int32_t* symmetric, double* eps) {
+  if (!k) return OTLM_E_INVALID;
+  if (n) *n = k->n;
+  if (symmetric) *symmetric = k->symmetric;
+  if (eps) *eps = k->eps;
+  return OTLM_OK;
+}
+
+int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y, int64_t B,
+                     const otlm_params* p, float* W, float* logU, float* logV, int32_t* iters,
+                     int32_t* status, void* stream) {
+  if (!k || !params_valid(p, k->eps)) return OTLM_E_INVALID;
+  if (B < 0 || kdim < 1 || kdim > 256) return OTLM_E_INVALID;
+  if (B == 0) return OTLM_OK;
+  if (!D || !Y || !W || !logV) return OTLM_E_INVALID;
+  if (B > (1 << 24)) return OTLM_E_INVALID;
+  if (p->prec != OTLM_PREC_FP32) return OTLM_E_UNSUPPORTED;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = k->n, np = k->np, kp = round_up(kdim, 64);
+  int rc = ensure_workspace(k, B, kp);
+  if (rc != OTLM_OK) return rc;
+  Workspace& ws = k->ws;
+
+  OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
+  hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
+                     p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
+  hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
+                     (const float4*)ws.colc, (int)n, (int)kdim, (int)np, (int)kp, p->warm, ws.V, ws.W, ws.U,
+                     ws.done, ws.status, ws.iters, ws.ew_prev, ws.flags + 1);
+  OTLM_HIP(hipGetLastError());
+  OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  OTLM_HIP(hipStreamSynchronize(s));
+  if (ws.host_flags[1]) return OTLM_E_INVALID;  // negative / non-finite D or Y, or an empty column
+
+  const int M = (int)B;
+  // a = D w for the start
+  {
+    GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
+    EpiStore e{ws.A, (int)np, (int)n, false};
+    gemm(64, 128, g, e, s);
+  }
+  const int bm_k = B >= 4096 ? 128 : 64, bn_k = 128;
+  const int nts = (int)((np + bn_k - 1) / bn_k);
+  const int bn_w = kp >= 128 ? 128 : 64;
+  const int ntw = (int)((kp + bn_w - 1) / bn_w);
+  ProxConsts pc;
+  pc.fit = p->fit;
+  pc.kappa = (float)(p->lambda / (p->lambda + p->eps));
+  pc.lam_eps = (float)(p->lambda / p->eps);
+  pc.lam2_eps = (float)(p->lambda2 / p->eps);
+  pc.eps_lam = p->lambda > 0 ? (float)(p->eps / p->lambda) : 0.f;
+  pc.log_lam_eps = p->lambda > 0 ? (float)std::log(p->lambda / p->eps) : 0.f;
+
+  int it = 0;
+  for (it = 1; it <= p->max_iter; ++it) {
+    const bool chk = (p->tol > 0.0) && (it % p->check_every == 0 || it == p->max_iter);
+    {  // s = K v, r = log(s / a)
+      ProfScope ps(k, 0, s);
+      GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
+      EpiSrc e{ws.S, ws.R, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
+      gemm(bm_k, bn_k, g, e, s);
+    }
+    {  // MM weight step
+      ProfScope ps(k, 1, s);
+      GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
+      EpiWupd e{ws.W, ws.colc, ws.done, ws.pwn, ws.pwd, (int)kp, (int)kdim, p->pen, ntw, chk};
+      gemm(64, bn_w, g, e, s);
+    }
+    {  // a = D w, u = a / s
+      ProfScope ps(k, 2, s);
+      GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
+      EpiUscale e{ws.A, ws.U, ws.S, (int)np, (int)n, false};
+      gemm(64, 128, g, e, s);
+    }
+    {  // t = K^T u, v = prox(t | y) / t
+      ProfScope ps(k, 3, s);
+      GemmArgs g{ws.U, (int)np, k->KT, (int)np, M, (int)np, (int)np};
+      EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false};
+      gemm(bm_k, bn_k, g, e, s);
+    }
+    if (chk) {
+      {
+        ProfScope ps(k, 4, s);
+        hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts, ws.pwn, ws.pwd, ntw, M,
+                           (float)p->tol, OTLM_FP32_FLOOR, p->check_every, it, ws.ew_prev, ws.done, ws.iters,
+                           ws.status, ws.flags);
+      }
+      OTLM_HIP(hipGetLastError());
+      OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+      OTLM_HIP(hipStreamSynchronize(s));
+      if (ws.host_flags[0] == 0) break;
+    }
+  }
+  OTLM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
+                     ws.iters, (int)n, (int)kdim, (int)np, (int)kp, p->max_iter, W, logU, logV, iters, status);
+  OTLM_HIP(hipGetLastError());
+  return OTLM_OK;
+}
+
+int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim, const float* Y, int64_t B,
+                   const otlm_params* p, const float* W, const float* logU, const float* logV, double* out,
+                   void* stream) {
+  if (!k || !params_valid(p, k->eps)) return OTLM_E_INVALID;
+  if (B < 0 || kdim < 1 || kdim > 256) return OTLM_E_INVALID;
+  if (B == 0) return OTLM_OK;
+  if (!C || !D || !Y || !W || !logU || !logV || !out) return OTLM_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace& ws = k->ws;
+  const int64_t n = k->n;
+  if (ws.obj_B < B) {
+    ws.release_obj();
+    if (hipMalloc(&ws.os, (size_t)B * n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ws.ot, (size_t)B * n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ws.oq, (size_t)B * n * sizeof(double)) != hipSuccess) {
+      ws.release_obj();
+      return OTLM_E_NOMEM;
+    }
+    ws.obj_B = B;
+  }
+  hipLaunchKernelGGL(objective_products, dim3((unsigned)((n + 3) / 4), (unsigned)B), dim3(256), 0, s, k->K64,
+                     k->KT64, C, logU, logV, (int)n, ws.os, ws.ot, ws.oq);
+  ObjParams op{(int)n, (int)kdim, p->fit, p->pen, p->eps, p->lambda, p->lambda2, p->alpha, p->beta, k->sumK};
+  hipLaunchKernelGGL(objective_reduce, dim3((unsigned)B), dim3(256), 0, s, op, D, Y, W, logU, logV, ws.os, ws.ot,
+                     ws.oq, out);
+  OTLM_HIP(hipGetLastError());
+  return OTLM_OK;
+}
+
+}  // extern "C"

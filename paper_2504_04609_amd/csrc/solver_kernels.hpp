@@ -1,0 +1,373 @@
+// Device side of the OTLM scaling loop (Algorithm 1): the GEMM epilogues that
+// carry each elementwise update, plus set-up, convergence and output kernels.
+//
+// Internal layout: every per-spectrum array is [B, ld] row-major FP32 with the
+// bin dimension padded to np (multiple of 16) and the dictionary dimension to
+// kp (multiple of 16); padded entries are kept at exactly 0 so they never
+// contribute to a product.  Notation follows the paper with u_1 -> v
+// (target-side scaling) and u_2 -> u (source-side scaling).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "omega.hpp"
+
+enum { FIT_BALANCED = 0, FIT_KL = 1, FIT_TV = 2, FIT_L2 = 3, FIT_L2_TV = 4, FIT_POISSON = 5 };
+enum { PEN_NONE = 0, PEN_L1 = 1, PEN_L2SQ = 2, PEN_EN = 3 };
+
+constexpr float OTLM_R_CLAMP = 1.0e30f;
+
+// ---------------------------------------------------------------------------
+// s = K v epilogue (Algorithm 1, source update, first half).
+// Stores s and r = log(s / a) with a = D w from the previous weight step
+// (Table 2: Z's normalisation (D w')_i; bins with a = 0 carry no dictionary
+// mass and contribute 0).  On check iterations it also accumulates the
+// source-marginal violation sum_i |u_i s_i - a_i| and sum_i a_i, where u is the
+// previous source scaling, so u o (K v) - D w measures how far the current plan
+// is from Q1 = D w.
+struct EpiSrc {
+  static constexpr int NRED = 2;
+  static constexpr bool RED_IS_MAX[2] = {false, false};
+  float* S;
+  float* R;
+  const float* A;
+  const float* U;
+  float* part_num;
+  float* part_den;
+  int ld, n_valid, ntiles;
+  bool do_red;
+  __device__ __forceinline__ void elem(int m, int n, float s, float* red) const {
+    const size_t o = (size_t)m * ld + n;
+    if (n >= n_valid) {
+      S[o] = 0.f;
+      R[o] = 0.f;
+      return;
+    }
+    const float a = A[o];
+    float r = 0.f;
+    if (a > 0.f) r = fminf(fmaxf(logf(s / a), -OTLM_R_CLAMP), OTLM_R_CLAMP);
+    S[o] = s;
+    R[o] = r;
+    if (do_red) {
+      red[0] += fabsf(U[o] * s - a);
+      red[1] += a;
+    }
+  }
+  __device__ __forceinline__ void row_partial(int m, int tile, const float* v) const {
+    part_num[(size_t)m * ntiles + tile] = v[0];
+    part_den[(size_t)m * ntiles + tile] = v[1];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Weight step epilogue: c = (R D)_j = sum_i D_ij log(s_i / a_i).
+// Table 2 / Appendix A: nu_j = log w'_j + c_j / x_j and
+//   none:        w_j = exp(nu_j)
+//   l1:          w_j = exp(nu_j - alpha / (eps x_j))
+//   squared l2:  w_j = omega(nu_j + log g_j) / g_j,              g_j = alpha / (eps x_j)
+//   elastic net: w_j = omega(nu_j - alpha/(eps x_j) + log g_j) / g_j,  g_j = beta / (eps x_j)
+// colc holds per column [1/x_j, shift_j, g_j, log g_j].  Frozen spectra keep
+// their weights.  Reductions: max_j |w_j - w'_j| and max_j |w_j|.
+struct EpiWupd {
+  static constexpr int NRED = 2;
+  static constexpr bool RED_IS_MAX[2] = {true, true};
+  float* W;
+  const float4* colc;
+  const int* done;
+  float* part_num;
+  float* part_den;
+  int ld, k_valid, pen, ntiles;
+  bool do_red;
+  __device__ __forceinline__ void elem(int m, int j, float c, float* red) const {
+    const size_t o = (size_t)m * ld + j;
+    if (j >= k_valid) {
+      W[o] = 0.f;
+      return;
+    }
+    const float wold = W[o];
+    const float4 cc = colc[j];
+    const float nu = logf(wold) + c * cc.x;
+    float w;
+    if (pen == PEN_NONE) {
+      w = expf(nu);
+    } else if (pen == PEN_L1) {
+      w = expf(nu - cc.y);
+    } else {  // PEN_L2SQ (shift 0) and PEN_EN share the Lambert-W form
+      w = wright_omega<float>(nu - cc.y + cc.w) / cc.z;
+    }
+    if (done[m]) w = wold;
+    else W[o] = w;
+    red[0] = fmaxf(red[0], fabsf(w - wold));
+    red[1] = fmaxf(red[1], fabsf(w));
+  }
+  __device__ __forceinline__ void row_partial(int m, int tile, const float* v) const {
+    part_num[(size_t)m * ntiles + tile] = v[0];
+    part_den[(size_t)m * ntiles + tile] = v[1];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// a = D w epilogue, then u = a / s (Algorithm 1: u_2 <- X w / K u_1).
+struct EpiUscale {
+  static constexpr int NRED = 0;
+  static constexpr bool RED_IS_MAX[2] = {false, false};
+  float* A;
+  float* U;
+  const float* S;
+  int ld, n_valid;
+  bool do_red;
+  __device__ __forceinline__ void elem(int m, int n, float a, float*) const {
+    const size_t o = (size_t)m * ld + n;
+    if (n >= n_valid) {
+      A[o] = 0.f;
+      U[o] = 0.f;
+      return;
+    }
+    a = fmaxf(a, 0.f);
+    A[o] = a;
+    U[o] = a > 0.f ? a / S[o] : 0.f;
+  }
+  __device__ __forceinline__ void row_partial(int, int, const float*) const {}
+};
+
+// Plain store epilogue (a = D w at set-up).
+struct EpiStore {
+  static constexpr int NRED = 0;
+  static constexpr bool RED_IS_MAX[2] = {false, false};
+  float* C;
+  int ld, n_valid;
+  bool do_red;
+  __device__ __forceinline__ void elem(int m, int n, float c, float*) const {
+    C[(size_t)m * ld + n] = n < n_valid ? c : 0.f;
+  }
+  __device__ __forceinline__ void row_partial(int, int, const float*) const {}
+};
+
+// ---------------------------------------------------------------------------
+// Target step (Table 1), for t = (K^T u)_j and data y_j, returns v_j = p_j / t_j.
+struct ProxConsts {
+  int fit;
+  float kappa;        // KL: lam / (lam + eps)
+  float lam_eps;      // lam / eps
+  float lam2_eps;     // lam2 / eps
+  float eps_lam;      // eps / lam
+  float log_lam_eps;  // log(lam / eps)
+};
+
+__device__ __forceinline__ float target_scaling(const ProxConsts& pc, float t, float y) {
+  if (!(t > 0.f)) return 1.f;  // no transported mass reaches this bin: leave v = 1
+  const float lt = logf(t);
+  switch (pc.fit) {
+    case FIT_BALANCED:
+      return y / t;
+    case FIT_KL:  // p = t^{eps/(eps+lam)} y^{lam/(eps+lam)}  ->  v = (y / t)^{lam/(eps+lam)}
+      return y > 0.f ? expf(pc.kappa * (logf(y) - lt)) : 0.f;
+    case FIT_TV: {  // p = min(t e^{lam/eps}, max(t e^{-lam/eps}, y))
+      const float ly = y > 0.f ? logf(y) : -INFINITY;
+      return expf(fminf(fmaxf(ly - lt, -pc.lam_eps), pc.lam_eps));
+    }
+    case FIT_L2: {  // p = (eps/lam) W0((lam/eps) t e^{lam y / eps})
+      const float p = pc.eps_lam * wright_omega<float>(pc.log_lam_eps + lt + pc.lam_eps * y);
+      return p / t;
+    }
+    case FIT_L2_TV: {  // tau = prox_TV(t), p = prox_L2(tau)
+      const float ly = y > 0.f ? logf(y) : -INFINITY;
+      const float ltau = lt + fminf(fmaxf(ly - lt, -pc.lam2_eps), pc.lam2_eps);
+      const float p = pc.eps_lam * wright_omega<float>(pc.log_lam_eps + ltau + pc.lam_eps * y);
+      return p / t;
+    }
+    case FIT_POISSON: {  // p = (lam/eps) y / W0((lam/eps) (y/t) e^{lam/eps})
+      if (!(y > 0.f)) return 0.f;
+      const float p = pc.lam_eps * y / wright_omega<float>(pc.log_lam_eps + logf(y) - lt + pc.lam_eps);
+      return p / t;
+    }
+  }
+  return 1.f;
+}
+
+struct EpiProx {
+  static constexpr int NRED = 0;
+  static constexpr bool RED_IS_MAX[2] = {false, false};
+  float* V;
+  const float* Y;
+  const int* done;
+  ProxConsts pc;
+  int ld, ldy, n_valid;
+  bool do_red;
+  __device__ __forceinline__ void elem(int m, int n, float t, float*) const {
+    const size_t o = (size_t)m * ld + n;
+    if (n >= n_valid) {
+      V[o] = 0.f;
+      return;
+    }
+    if (done[m]) return;
+    V[o] = target_scaling(pc, t, Y[(size_t)m * ldy + n]);
+  }
+  __device__ __forceinline__ void row_partial(int, int, const float*) const {}
+};
+
+// ---------------------------------------------------------------------------
+// Set-up and bookkeeping kernels.
+
+// K = exp(-C / eps) in FP64, rounded to FP32, zero-padded to [np, np].
+// With transpose=1 the output is K^T.
+__global__ void build_kernel_f32(const double* __restrict__ C, int n, int np, double inv_eps, int transpose,
+                                 float* __restrict__ K) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= np || i >= np) return;
+  float v = 0.f;
+  if (i < n && j < n) v = (float)exp(-(transpose ? C[(size_t)j * n + i] : C[(size_t)i * n + j]) * inv_eps);
+  K[(size_t)i * np + j] = v;
+}
+
+// Dictionary copies: Dp [np, kp] (= D, zero padded), DTp [kp, np] (= D^T),
+// per-column constants colc[j] = {1/x_j, shift_j, gamma_j, log gamma_j}.
+__global__ void prep_dictionary(const float* __restrict__ D, int n, int k, int np, int kp, int pen, double eps,
+                                double alpha, double beta, float* __restrict__ Dp, float* __restrict__ DTp,
+                                float4* __restrict__ colc, int* __restrict__ bad) {
+  const int j = blockIdx.x;
+  if (j >= kp) return;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const float d = (i < n && j < k) ? D[(size_t)i * k + j] : 0.f;
+    Dp[(size_t)i * kp + j] = d;
+    DTp[(size_t)j * np + i] = d;
+    if (!(d >= 0.f) || !isfinite(d)) bad[0] = 1;
+  }
+  if (threadIdx.x == 0) {
+    float4 c = {0.f, 0.f, 1.f, 0.f};
+    if (j < k) {
+      double x = 0.0;
+      for (int i = 0; i < n; ++i) x += (double)D[(size_t)i * k + j];
+      if (!(x > 0.0)) bad[0] = 1;
+      double shift = 0.0, gam = 1.0;
+      if (pen == PEN_L1) shift = alpha / (eps * x);
+      if (pen == PEN_L2SQ) gam = alpha / (eps * x);
+      if (pen == PEN_EN) {
+        shift = alpha / (eps * x);
+        gam = beta / (eps * x);
+      }
+      c = make_float4((float)(1.0 / x), (float)shift, (float)gam, (float)log(gam));
+    }
+    colc[j] = c;
+  }
+}
+
+// Per-spectrum set-up: validity of y, total mass, and the initial state
+// (cold: v = 1, w0_j = sum(y) / (k x_j); warm: v = exp(logV), w = W).
+// One workgroup per spectrum.
+__global__ void init_state(const float* __restrict__ Y, const float* __restrict__ Win,
+                           const float* __restrict__ logVin, const float4* __restrict__ colc, int n, int k,
+                           int np, int kp, int warm, float* __restrict__ V, float* __restrict__ W,
+                           float* __restrict__ U, int* __restrict__ done, int* __restrict__ status,
+                           int* __restrict__ iters, float* __restrict__ ew_prev, int* __restrict__ bad) {
+  const int b = blockIdx.x;
+  __shared__ double ssum[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const size_t o = (size_t)b * np + i;
+    if (i < n) {
+      const float y = Y[(size_t)b * n + i];
+      if (!(y >= 0.f) || !isfinite(y)) bad[0] = 1;
+      acc += (double)y;
+      V[o] = warm ? expf(logVin[(size_t)b * n + i]) : 1.f;
+    } else {
+      V[o] = 0.f;
+    }
+    U[o] = 0.f;
+  }
+  ssum[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double mass = ssum[0];
+  for (int j = threadIdx.x; j < kp; j += blockDim.x) {
+    float w = 0.f;
+    if (j < k) w = warm ? Win[(size_t)b * k + j] : (float)(mass / k * (double)colc[j].x);
+    W[(size_t)b * kp + j] = w;
+  }
+  if (threadIdx.x == 0) {
+    done[b] = 0;
+    status[b] = 0;
+    iters[b] = 0;
+    ew_prev[b] = 0.f;
+  }
+}
+
+// Convergence test for every spectrum (the stopping rule of "while not
+// converged"): e_src = sum|u s - a| / sum a and e_w = max|dw| / max|w|, both
+// assembled from the per-tile partials in a fixed order.  The weight test uses
+// the a-posteriori bound of a linearly converging iteration: with the observed
+// contraction rho = (e_w / e_w_prev)^(1/c) over the c iterations since the last
+// test, the distance to the limit is about e_w rho / (1 - rho).  A spectrum
+// stops when e_src <= tol and either that bound is <= tol or e_w has reached
+// the FP32 resolution `floor` (the iteration cannot move w any further).  One
+// workgroup; also counts the spectra still active into *active.
+__global__ void check_convergence(const float* __restrict__ psn, const float* __restrict__ psd, int nts,
+                                  const float* __restrict__ pwn, const float* __restrict__ pwd, int ntw, int B,
+                                  float tol, float floor_w, int c, int it, float* __restrict__ ew_prev,
+                                  int* __restrict__ done, int* __restrict__ iters, int* __restrict__ status,
+                                  int* __restrict__ active) {
+  __shared__ int cnt[1024];
+  int count = 0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    if (!done[b]) {
+      float num = 0.f, den = 0.f, dw = 0.f, wm = 0.f;
+      for (int t = 0; t < nts; ++t) {
+        num += psn[(size_t)b * nts + t];
+        den += psd[(size_t)b * nts + t];
+      }
+      for (int t = 0; t < ntw; ++t) {
+        dw = fmaxf(dw, pwn[(size_t)b * ntw + t]);
+        wm = fmaxf(wm, pwd[(size_t)b * ntw + t]);
+      }
+      const float esrc = den > 0.f ? num / den : 0.f;
+      const float ew = wm > 0.f ? dw / wm : 0.f;
+      const float prev = ew_prev[b];
+      ew_prev[b] = ew;
+      float bound = INFINITY;
+      if (ew == 0.f) {
+        bound = 0.f;
+      } else if (prev > 0.f && ew < prev) {
+        const float rho = powf(ew / prev, 1.f / (float)c);
+        bound = ew * rho / (1.f - rho);
+      }
+      if (!isfinite(num + den + dw + wm)) {
+        done[b] = 1;
+        status[b] = 4;
+        iters[b] = it;
+      } else if (esrc <= tol && (bound <= tol || ew <= floor_w)) {
+        done[b] = 1;
+        status[b] = 1;
+        iters[b] = it;
+      } else {
+        ++count;
+      }
+    }
+  }
+  cnt[threadIdx.x] = count;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) active[0] = cnt[0];
+}
+
+// Outputs: W (unpadded), log u, log v, iteration counts and status flags.
+__global__ void write_outputs(const float* __restrict__ Wst, const float* __restrict__ U,
+                              const float* __restrict__ V, const int* __restrict__ done,
+                              const int* __restrict__ st, const int* __restrict__ it_in, int n, int k, int np,
+                              int kp, int max_iter, float* __restrict__ W, float* __restrict__ logU,
+                              float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
+  const int b = blockIdx.x;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) W[(size_t)b * k + j] = Wst[(size_t)b * kp + j];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if (logU) logU[(size_t)b * n + i] = logf(U[(size_t)b * np + i]);
+    logV[(size_t)b * n + i] = logf(V[(size_t)b * np + i]);
+  }
+  if (threadIdx.x == 0) {
+    if (iters) iters[b] = done[b] ? it_in[b] : max_iter;
+    if (status) status[b] = done[b] ? st[b] : 2;
+  }
+}
