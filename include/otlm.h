@@ -62,38 +62,67 @@ typedef enum {
 } otlm_penalty;
 
 typedef enum {
-  OTLM_PREC_FP32 = 0,          /* FP32 kernel products on MFMA, FP32 updates */
-  OTLM_PREC_BF16_REFINE = 1    /* BF16 products (FP32 accumulate), then FP32 sweeps */
+  OTLM_PREC_FP32 = 0,          /* FP32 kernel products on MFMA, FP32 state             */
+  OTLM_PREC_BF16 = 1           /* BF16 kernel products (FP32 accumulate), FP32 state   */
 } otlm_precision;
+
+typedef enum {
+  OTLM_REFINE_NONE = 0,        /* no refinement phase                                   */
+  OTLM_REFINE_FP32 = 1,        /* FP32 products and state                               */
+  OTLM_REFINE_FP64 = 2         /* FP64 products (MFMA f64) and state                    */
+} otlm_refine;
+
+enum { OTLM_WSTEP_MM = 0, OTLM_WSTEP_EXACT = 1 };
 
 /* Per-spectrum outcome flags written to status[b]. */
 enum {
-  OTLM_S_CONVERGED = 1,   /* weight change and source violation <= tol          */
-  OTLM_S_MAX_ITER = 2,    /* stopped at max_iter                                 */
-  OTLM_S_NONFINITE = 4    /* a NaN/Inf appeared; the spectrum was frozen         */
+  OTLM_S_CONVERGED = 1,   /* the stopping test passed                                */
+  OTLM_S_MAX_ITER = 2,    /* stopped at the iteration cap                            */
+  OTLM_S_NONFINITE = 4,   /* a NaN/Inf appeared; the spectrum was frozen             */
+  OTLM_S_STAGNATED = 8    /* the weight change stopped improving for 6 tests: the
+                             noise floor of the phase precision was reached        */
 };
 
+/* Solver parameters.  A solve has a bulk phase in precision `prec` and, when
+ * `refine` is not NONE, a refinement phase in precision `refine` that starts
+ * from the bulk result.  Each phase freezes a spectrum once its own test
+ * passes: the stopping rule of "while not converged" is
+ *   sum|u o (K v) - D w| / sum(D w) <= tol_phase   and
+ *   max|dw| / max|w| * rho / (1 - rho) <= tol_phase (rho = observed contraction
+ *   between tests) or max|dw| / max|w| below the phase precision's resolution.
+ * tol_phase is `bulk_tol` for a bulk phase followed by refinement, `tol`
+ * otherwise. */
 typedef struct {
   double eps;            /* entropic regulariser, > 0 (must equal the kernel's)   */
   double lambda;         /* datafit weight, >= 0                                   */
   double lambda2;        /* TV weight of OTLM_FIT_L2_TV, >= 0                      */
   double alpha;          /* penalty weight, >= 0 (> 0 for L2SQ)                    */
   double beta;           /* quadratic weight of OTLM_PEN_ELASTIC, > 0 there        */
-  double tol;            /* stop a spectrum when max|dw|/max|w| <= tol and
-                            sum|u*(Kv) - Dw| / sum(Dw) <= tol; 0 = run max_iter   */
-  int32_t max_iter;      /* >= 1                                                   */
+  double tol;            /* final stopping tolerance, >= 0 (0 = run to the caps)   */
+  double bulk_tol;       /* bulk-phase tolerance when a refinement follows, >= 0   */
+  int32_t max_iter;      /* iteration cap of the bulk phase, >= 1                  */
   int32_t check_every;   /* convergence test cadence in iterations, >= 1           */
   int32_t fit;           /* otlm_datafit                                           */
   int32_t pen;           /* otlm_penalty                                           */
-  int32_t prec;          /* otlm_precision                                         */
+  int32_t prec;          /* otlm_precision of the bulk phase                       */
+  int32_t refine;        /* otlm_refine                                            */
+  int32_t refine_sweeps; /* iteration cap of the refinement phase, >= 1 if used    */
   int32_t warm;          /* 0: cold start (w0_j = sum(y)/(k x_j), v = 1);
                             1: start from the W and logV arrays passed in          */
-  int32_t refine_sweeps; /* FP32 sweeps after the BF16 phase (BF16_REFINE)         */
-  int32_t reserved;
+  int32_t wstep;         /* weight step per iteration: OTLM_WSTEP_MM (one MM step,
+                            Table 2, as in Algorithm 1) or OTLM_WSTEP_EXACT (the
+                            weight prox ProxP solved by an active-set Newton
+                            method, the run-to-convergence alternative of
+                            subsection "Iterative Algorithm for OTLM"; needs
+                            kdim <= 64 and n <= 1024; the first 3 iterations of
+                            a cold start take the MM step)                          */
+  int32_t inner_max;     /* Newton iterations per weight prox (WSTEP_EXACT), >= 1  */
 } otlm_params;
 
 /* Fill `p` with defaults: KL datafit, no penalty, eps = lambda = 1, tol 1e-6,
- * max_iter 1000, check_every 10, FP32, cold start. */
+ * bulk_tol 1e-4, max_iter 1000, check_every 10, FP32, no refinement
+ * (refine_sweeps 200 when enabled), cold start, one MM step per iteration,
+ * inner_max 5. */
 void otlm_default_params(otlm_params* p);
 
 /* Build the Gibbs kernel K = exp(-C / eps) (Algorithm 1, initialisation).
@@ -125,15 +154,18 @@ int otlm_kernel_info(otlm_kernel k, int64_t* n, int32_t* symmetric, double* eps)
  *   logU    device FP32 [B, n] or NULL: output log of the source scaling u.
  *   logV    device FP32 [B, n]: output log of the target scaling v; read as
  *           the start when p->warm == 1.
- *   iters   device int32 [B] or NULL: iteration at which each spectrum
- *           stopped (a multiple of check_every, or max_iter).
+ *   iters   device int32 [B] or NULL: iterations each spectrum took over
+ *           both phases (the stopping test runs every check_every
+ *           iterations).
  *   status  device int32 [B] or NULL: OTLM_S_* flags.
  * Each spectrum is frozen once its own test passes, so its result does not
  * depend on the other spectra of the batch.  The host thread blocks once per
  * `check_every` iterations to read the number of active spectra.
  * Errors: OTLM_E_INVALID (bad sizes or parameters: eps must equal the
- * kernel's, 1 <= kdim <= 256, B >= 0), OTLM_E_UNSUPPORTED, OTLM_E_NOMEM,
- * OTLM_E_HIP.  B = 0 is a no-op. */
+ * kernel's, 1 <= kdim <= 256, B >= 0; negative or non-finite D or Y, or a D
+ * column summing to 0), OTLM_E_UNSUPPORTED (WSTEP_EXACT beyond its sizes,
+ * REFINE_FP64 without WSTEP_EXACT), OTLM_E_NOMEM, OTLM_E_HIP.  B = 0 is a
+ * no-op. */
 int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y, int64_t B,
                      const otlm_params* p, float* W, float* logU, float* logV,
                      int32_t* iters, int32_t* status, void* stream);

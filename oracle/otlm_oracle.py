@@ -16,8 +16,8 @@ Models"):
   (section "MM for Penalized Column Span Projection with KL Divergence");
 * the exact weight proximal step (ProxP in section "Scaling Algorithm Framework
   for OTLM"), which the paper allows in place of the single MM step (subsection
-  "Iterative Algorithm for OTLM"); its minimiser is computed here by a projected
-  Newton method on the same objective V(w);
+  "Iterative Algorithm for OTLM"); its minimiser is computed here by an
+  active-set Newton method on the same objective V(w);
 * the objective of the OTLM problem (eq. OTLM, in the scaling-algorithm form
   eps KL(Q|K) + F1(Q1) + F2(Q^T 1)), its Fenchel dual and KKT residuals.
 
@@ -192,55 +192,82 @@ def prox_objective(w, s, D, pen, eps, alpha, beta=0.0):
 
 
 def prox_P_exact(s, D, w0, pen: str, eps: float, alpha: float, beta: float = 0.0,
-                 max_newton: int = 500, rtol: float = 1e-15):
+                 max_newton: int = 500, gtol: float = 1e-13):
     """Exact weight prox: argmin_{w >= 0} alpha R(w) + eps KL(Dw || s)  (ProxP).
 
-    Projected Newton method (two-metric projection) on the smooth convex
-    objective V(w): gradient alpha R'(w) + eps D^T log(Dw / s), Hessian
-    alpha R'' + eps D^T diag(1 / Dw) D.  A step never moves a weight below a
-    hundredth of its value (the KL term has an infinite slope where a covered
-    bin loses all its mass), and a weight is fixed at exactly 0 only once it is
-    negligible and its gradient is positive.  One spectrum at a time.
+    Active-set Newton method on the smooth convex objective V(w), gradient
+    alpha R'(w) + eps D^T log(Dw / s), Hessian alpha R'' + eps D^T diag(1/Dw) D:
+    Newton steps on the free weights with a ratio test that stops at the first
+    weight reaching 0 (which then joins the active set) and Armijo backtracking;
+    the active weight with the most negative gradient is released once the free
+    gradient is small next to it (or no descent is left on the free set).  Ends
+    when the free gradient is below ``gtol`` (scaled) and no active weight has a
+    negative gradient.  One spectrum at a time.
     """
-    w = np.array(w0, dtype=np.float64)
+    w = np.maximum(np.array(w0, dtype=np.float64), 0.0)
     cover = D.sum(axis=1) > 0                # bins in the support of the dictionary
     Dc, sc = D[cover], s[cover]
     hess_pen = {"none": 0.0, "l1": 0.0, "l2sq": alpha, "en": beta}[pen]
+    tiny = 1e-300
+    gscale = max(alpha, eps, 1e-300)
 
     def V(ww):
         return prox_objective(ww, sc, Dc, pen, eps, alpha, beta)
 
+    act = w <= 0.0
     f = V(w)
     for _ in range(max_newton):
-        a = Dc @ w
-        with np.errstate(divide="ignore"):
-            grad = penalty_grad(w, pen, alpha, beta) + eps * (Dc.T @ np.log(a / sc))
-        scale = max(w.max(), 1e-300)
-        binding = (w <= 1e-14 * scale) & (grad > 0)
-        free = ~binding
-        d = np.zeros_like(w)
-        if free.any():
-            Df = Dc[:, free]
-            H = eps * (Df.T * (1.0 / a)) @ Df + hess_pen * np.eye(int(free.sum()))
-            try:
-                d[free] = -np.linalg.solve(H, grad[free])
-            except np.linalg.LinAlgError:
-                d[free] = -np.linalg.lstsq(H, grad[free], rcond=None)[0]
-        step, accepted = 1.0, False
-        while step > 1e-20:
-            wn = np.maximum(w + step * d, 0.01 * w)
-            wn[binding] = 0.0
-            fn = V(wn)
-            if fn <= f + 1e-4 * (grad[free] @ (wn - w)[free]):
-                accepted = True
-                break
-            step *= 0.5
-        if not accepted:
+        a = np.maximum(Dc @ w, tiny)
+        g = penalty_grad(w, pen, alpha, beta) + eps * (Dc.T @ np.log(a / sc))
+        free = ~act
+        kkt = np.max(np.abs(g[free])) if free.any() else 0.0
+        cand = np.flatnonzero(act & (g < -gtol * gscale))
+        jmin = cand[np.argmin(g[cand])] if cand.size else -1
+        if kkt <= gtol * gscale and jmin < 0:
+            break                              # optimal
+        released = -1
+        if jmin >= 0 and kkt <= max(gtol * gscale, 0.1 * abs(g[jmin])):
+            act[jmin] = False                  # free problem solved well enough: release
+            free = ~act
+            released, jmin = jmin, -1
+        F = np.flatnonzero(free)
+        Df = Dc[:, F]
+        H = eps * (Df.T * (1.0 / a)) @ Df + hess_pen * np.eye(F.size)
+        try:
+            d = -np.linalg.solve(H, g[F])
+        except np.linalg.LinAlgError:
+            d = -np.linalg.lstsq(H, g[F], rcond=None)[0]
+        d[(w[F] <= 0.0) & (d < 0.0)] = 0.0     # weights at 0 cannot decrease
+        if released >= 0:
+            r = int(np.flatnonzero(F == released)[0])
+            if d[r] <= 0.0:                    # coupling swamped the released weight:
+                d[:] = 0.0                     # take its own Newton coordinate step
+                d[r] = -g[released] / H[r, r]
+        neg = d < 0
+        tmax = float(np.min(-w[F][neg] / d[neg])) if neg.any() else np.inf
+        t = min(1.0, tmax)
+        slope = float(g[F] @ d)
+        accepted = False
+        if slope < 0:
+            while t >= 1e-18:
+                wn = w.copy()
+                wn[F] = np.maximum(w[F] + t * d, 0.0)
+                fn = V(wn)
+                if fn <= f + 1e-4 * t * slope:
+                    accepted = True
+                    break
+                t *= 0.5
+        if not accepted:                       # no descent left on this free set
+            if jmin >= 0:
+                act[jmin] = False
+                continue
             break
-        change = np.max(np.abs(wn - w))
-        w, f = wn, fn
-        if change <= rtol * max(w.max(), 1e-300):
-            break
+        if t == tmax:                          # the blocking weights join the active set
+            blk = neg & (-w[F] / np.where(neg, d, -1.0) <= tmax * (1.0 + 1e-12))
+            z = F[blk]
+            act[z] = True
+            wn[z] = 0.0
+        w, f = wn, V(wn)
     return w
 
 
@@ -255,7 +282,7 @@ def initial_weights(Y, D):
 
 def solve(K, D, Y, *, fit="kl", pen="l1", eps=0.01, lam=1.0, alpha=0.0, lam2=0.0,
           beta=0.0, max_iter=1000, tol=0.0, mode="single", W0=None, V0=None,
-          trace=None):
+          trace=None, mm_warmup=3):
     """Algorithm 1 on a batch of targets Y [B, n] sharing K and D.
 
     Per iteration (Algorithm 1, in order):
@@ -263,6 +290,9 @@ def solve(K, D, Y, *, fit="kl", pen="l1", eps=0.01, lam=1.0, alpha=0.0, lam2=0.0
       u = D w / s;  t = K^T u;  p = prox_L(t | y);  v = p / t.
     Each spectrum stops on its own (and is frozen) once both the weight change
     and the source-marginal violation are <= tol; ``tol = 0`` runs max_iter.
+    In mode "exact" the first ``mm_warmup`` iterations still take the single MM
+    step: from a cold start s = K 1 carries far more mass than y, and an exact
+    prox there drives weights to scales from which Newton recovers slowly.
 
     Returns a dict with W [B,k], logU [B,n], logV [B,n], iters [B] and
     converged [B].
@@ -287,7 +317,7 @@ def solve(K, D, Y, *, fit="kl", pen="l1", eps=0.01, lam=1.0, alpha=0.0, lam2=0.0
         with np.errstate(invalid="ignore", divide="ignore"):
             e_src = (np.abs(U[act] * S - Aa).sum(axis=1) / Aa.sum(axis=1)
                      if it > 1 else np.full(Va.shape[0], np.inf))
-        if mode == "single":
+        if mode == "single" or (mode == "exact" and it <= mm_warmup):
             Wn = mm_step(Wa, S, D, pen, eps, alpha, beta)
         elif mode == "exact":
             Wn = np.stack([prox_P_exact(S[b], D, Wa[b], pen, eps, alpha, beta)

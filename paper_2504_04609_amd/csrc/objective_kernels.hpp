@@ -15,6 +15,17 @@ __global__ void build_kernel_f64(const double* __restrict__ C, int n, double inv
   K[(size_t)i * n + j] = exp(-(transpose ? C[(size_t)j * n + i] : C[(size_t)i * n + j]) * inv_eps);
 }
 
+// K = exp(-C / eps) in FP64, zero padded to [np, np] (refinement products).
+__global__ void build_kernel_f64p(const double* __restrict__ C, int n, int np, double inv_eps, int transpose,
+                                  double* __restrict__ K) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= np || i >= np) return;
+  double v = 0.0;
+  if (i < n && j < n) v = exp(-(transpose ? C[(size_t)j * n + i] : C[(size_t)i * n + j]) * inv_eps);
+  K[(size_t)i * np + j] = v;
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -21,8 +21,11 @@
 
 #include "../../include/otlm.h"
 #include "gemm_nt.hpp"
+#include "gemm_nt_f64.hpp"
 #include "objective_kernels.hpp"
+#include "prox_newton.hpp"
 #include "solver_kernels.hpp"
+#include "solver_kernels64.hpp"
 
 namespace {
 
@@ -45,6 +48,12 @@ struct Workspace {
   float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr;
   int *done = nullptr, *iters = nullptr, *status = nullptr, *flags = nullptr;
   float* ew_prev = nullptr;
+  float* ew_best = nullptr;
+  int* stall = nullptr;
+  // FP64 refinement state
+  int64_t B64 = 0;
+  double *V64 = nullptr, *S64 = nullptr, *A64 = nullptr, *U64 = nullptr, *W64 = nullptr, *Dp64 = nullptr;
+  std::vector<void*> allocs64;
   double *os = nullptr, *ot = nullptr, *oq = nullptr;
   int64_t obj_B = 0;
   int* host_flags = nullptr;  // pinned: [0] active count, [1] bad-input flag
@@ -60,6 +69,14 @@ struct Workspace {
     colc = nullptr;
     done = iters = status = flags = nullptr;
     ew_prev = nullptr;
+    ew_best = nullptr;
+    stall = nullptr;
+  }
+  void release64() {
+    for (void* p : allocs64) (void)hipFree(p);
+    allocs64.clear();
+    B64 = 0;
+    V64 = S64 = A64 = U64 = W64 = Dp64 = nullptr;
   }
   void release_obj() {
     if (os) (void)hipFree(os);
@@ -70,7 +87,12 @@ struct Workspace {
   }
 };
 
+// In the exact weight-prox mode the first iterations take the MM step: from a
+// cold start s = K 1 carries far more mass than y and an exact prox there
+// drives weights to scales that Newton leaves only slowly.
+constexpr int OTLM_MM_WARMUP = 3;
 constexpr float OTLM_FP32_FLOOR = 4.76837158e-7f;  // 2^-21: weight changes below it are FP32 noise
+constexpr float OTLM_FP64_FLOOR = 1e-13f;          // the same for the FP64 state
 constexpr int MAX_TILES = 256;  // per-row partial slots: np / 64 <= 256 column tiles
 
 }  // namespace
@@ -84,6 +106,8 @@ struct otlm_kernel_s {
   float* KT = nullptr;    // == K when symmetric
   double* K64 = nullptr;  // [n, n] FP64
   double* KT64 = nullptr; // == K64 when symmetric
+  double* K64p = nullptr;  // [np, np] FP64, zero padded (refinement products)
+  double* KT64p = nullptr; // == K64p when symmetric
   double sumK = 0.0;
   Workspace ws;
   // kernel timing (otlm_profile_*)
@@ -130,6 +154,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.status, (size_t)B);
   rc |= dev_alloc(ws, &ws.flags, 4);
   rc |= dev_alloc(ws, &ws.ew_prev, (size_t)B);
+  rc |= dev_alloc(ws, &ws.ew_best, (size_t)B);
+  rc |= dev_alloc(ws, &ws.stall, (size_t)B);
   if (rc != OTLM_OK) {
     ws.release();
     return OTLM_E_NOMEM;
@@ -208,6 +234,12 @@ bool params_valid(const otlm_params* p, double kernel_eps) {
   if ((p->fit == OTLM_FIT_L2 || p->fit == OTLM_FIT_L2_TV || p->fit == OTLM_FIT_POISSON) && !(p->lambda > 0.0))
     return false;
   if (p->warm != 0 && p->warm != 1) return false;
+  if (p->wstep != OTLM_WSTEP_MM && p->wstep != OTLM_WSTEP_EXACT) return false;
+  if (p->wstep == OTLM_WSTEP_EXACT && p->inner_max < 1) return false;
+  if (p->prec != OTLM_PREC_FP32 && p->prec != OTLM_PREC_BF16) return false;
+  if (p->refine < OTLM_REFINE_NONE || p->refine > OTLM_REFINE_FP64) return false;
+  if (p->refine != OTLM_REFINE_NONE && p->refine_sweeps < 1) return false;
+  if (!(p->bulk_tol >= 0.0)) return false;
   return true;
 }
 
@@ -226,6 +258,11 @@ void otlm_default_params(otlm_params* p) {
   p->fit = OTLM_FIT_KL;
   p->pen = OTLM_PEN_NONE;
   p->prec = OTLM_PREC_FP32;
+  p->refine = OTLM_REFINE_NONE;
+  p->refine_sweeps = 200;
+  p->bulk_tol = 1e-4;
+  p->wstep = OTLM_WSTEP_MM;
+  p->inner_max = 5;
 }
 
 const char* otlm_status_str(int code) {
@@ -270,15 +307,18 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
   k->symmetric = sym ? 1 : 0;
   const size_t npp = (size_t)k->np * k->np;
   if (hipMalloc(&k->K, npp * sizeof(float)) != hipSuccess ||
-      hipMalloc(&k->K64, (size_t)n * n * sizeof(double)) != hipSuccess) {
+      hipMalloc(&k->K64, (size_t)n * n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->K64p, npp * sizeof(double)) != hipSuccess) {
     otlm_free_kernel(k);
     return OTLM_E_NOMEM;
   }
   if (sym) {
     k->KT = k->K;
     k->KT64 = k->K64;
+    k->KT64p = k->K64p;
   } else if (hipMalloc(&k->KT, npp * sizeof(float)) != hipSuccess ||
-             hipMalloc(&k->KT64, (size_t)n * n * sizeof(double)) != hipSuccess) {
+             hipMalloc(&k->KT64, (size_t)n * n * sizeof(double)) != hipSuccess ||
+             hipMalloc(&k->KT64p, npp * sizeof(double)) != hipSuccess) {
     otlm_free_kernel(k);
     return OTLM_E_NOMEM;
   }
@@ -286,9 +326,11 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
   dim3 g32((unsigned)((k->np + 255) / 256), (unsigned)k->np), g64((unsigned)((n + 255) / 256), (unsigned)n);
   hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->K);
   hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 0, k->K64);
+  hipLaunchKernelGGL(build_kernel_f64p, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->K64p);
   if (!sym) {
     hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KT);
     hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 1, k->KT64);
+    hipLaunchKernelGGL(build_kernel_f64p, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KT64p);
   }
   if (hipGetLastError() != hipSuccess) {
     otlm_free_kernel(k);
@@ -335,7 +377,10 @@ int otlm_free_kernel(otlm_kernel k) {
     (void)hipEventDestroy(e.second);
   }
   k->ws.release();
+  k->ws.release64();
   k->ws.release_obj();
+  if (k->KT64p && k->KT64p != k->K64p) (void)hipFree(k->KT64p);
+  if (k->K64p) (void)hipFree(k->K64p);
   if (k->KT && k->KT != k->K) (void)hipFree(k->KT);
   if (k->K) (void)hipFree(k->K);
   if (k->KT64 && k->KT64 != k->K64) (void)hipFree(k->KT64);
@@ -361,26 +406,46 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   if (!D || !Y || !W || !logV) return OTLM_E_INVALID;
   if (B > (1 << 24)) return OTLM_E_INVALID;
   if (p->prec != OTLM_PREC_FP32) return OTLM_E_UNSUPPORTED;
+  const bool exact = p->wstep == OTLM_WSTEP_EXACT;
+  const bool fp64 = p->refine == OTLM_REFINE_FP64;
+  if (exact && (kdim > PN_K || prox_newton_smem((int)k->n, sizeof(double)) > 65536)) return OTLM_E_UNSUPPORTED;
+  if (fp64 && !exact) return OTLM_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = k->n, np = k->np, kp = round_up(kdim, 64);
   int rc = ensure_workspace(k, B, kp);
   if (rc != OTLM_OK) return rc;
   Workspace& ws = k->ws;
+  if (fp64 && ws.B64 < B) {
+    ws.release64();
+    const size_t bn = (size_t)B * np;
+    auto al = [&](double** q, size_t c) {
+      void* v = nullptr;
+      if (hipMalloc(&v, c * sizeof(double)) != hipSuccess) return false;
+      ws.allocs64.push_back(v);
+      *q = static_cast<double*>(v);
+      return true;
+    };
+    if (!al(&ws.V64, bn) || !al(&ws.S64, bn) || !al(&ws.A64, bn) || !al(&ws.U64, bn) ||
+        !al(&ws.W64, (size_t)B * kp) || !al(&ws.Dp64, (size_t)np * kp)) {
+      ws.release64();
+      return OTLM_E_NOMEM;
+    }
+    ws.B64 = B;
+  }
 
   OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
                      p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
                      (const float4*)ws.colc, (int)n, (int)kdim, (int)np, (int)kp, p->warm, ws.V, ws.W, ws.U,
-                     ws.done, ws.status, ws.iters, ws.ew_prev, ws.flags + 1);
+                     ws.done, ws.status, ws.iters, ws.ew_prev, ws.ew_best, ws.stall, ws.flags + 1);
   OTLM_HIP(hipGetLastError());
   OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   OTLM_HIP(hipStreamSynchronize(s));
   if (ws.host_flags[1]) return OTLM_E_INVALID;  // negative / non-finite D or Y, or an empty column
 
   const int M = (int)B;
-  // a = D w for the start
-  {
+  {  // a = D w for the start
     GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
     EpiStore e{ws.A, (int)np, (int)n, false};
     gemm(64, 128, g, e, s);
@@ -388,7 +453,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   const int bm_k = B >= 4096 ? 128 : 64, bn_k = 128;
   const int nts = (int)((np + bn_k - 1) / bn_k);
   const int bn_w = kp >= 128 ? 128 : 64;
-  const int ntw = (int)((kp + bn_w - 1) / bn_w);
+  const int ntw = exact ? 1 : (int)((kp + bn_w - 1) / bn_w);
   ProxConsts pc;
   pc.fit = p->fit;
   pc.kappa = (float)(p->lambda / (p->lambda + p->eps));
@@ -396,17 +461,44 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   pc.lam2_eps = (float)(p->lambda2 / p->eps);
   pc.eps_lam = p->lambda > 0 ? (float)(p->eps / p->lambda) : 0.f;
   pc.log_lam_eps = p->lambda > 0 ? (float)std::log(p->lambda / p->eps) : 0.f;
+  ProxConsts64 pc64;
+  pc64.fit = p->fit;
+  pc64.kappa = p->lambda / (p->lambda + p->eps);
+  pc64.lam_eps = p->lambda / p->eps;
+  pc64.lam2_eps = p->lambda2 / p->eps;
+  pc64.eps_lam = p->lambda > 0 ? p->eps / p->lambda : 0.0;
+  pc64.log_lam_eps = p->lambda > 0 ? std::log(p->lambda / p->eps) : 0.0;
 
-  int it = 0;
-  for (it = 1; it <= p->max_iter; ++it) {
-    const bool chk = (p->tol > 0.0) && (it % p->check_every == 0 || it == p->max_iter);
+  auto prox_args32 = [&]() {
+    ProxNewtonArgs<float, float> a;
+    a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
+    a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
+    return a;
+  };
+  auto prox_args64 = [&]() {
+    ProxNewtonArgs<double, double> a;
+    a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
+    a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
+    return a;
+  };
+
+  // One FP32 iteration (bulk phase or FP32 refinement); `it` counts from 1 over the whole solve.
+  auto iterate32 = [&](int it, bool chk) {
+    const bool mm_step = !exact || it <= OTLM_MM_WARMUP;
     {  // s = K v, r = log(s / a)
       ProfScope ps(k, 0, s);
       GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
-      EpiSrc e{ws.S, ws.R, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
+      EpiSrc e{ws.S, mm_step ? ws.R : nullptr, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
       gemm(bm_k, bn_k, g, e, s);
     }
-    {  // MM weight step
+    if (!mm_step) {  // weight prox solved by active-set Newton
+      ProfScope ps(k, 1, s);
+      auto kern = prox_newton_kernel<float, float>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
+                         prox_newton_smem((int)n, sizeof(float)), s, prox_args32());
+    } else {  // MM weight step
       ProfScope ps(k, 1, s);
       GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
       EpiWupd e{ws.W, ws.colc, ws.done, ws.pwn, ws.pwd, (int)kp, (int)kdim, p->pen, ntw, chk};
@@ -424,22 +516,90 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false};
       gemm(bm_k, bn_k, g, e, s);
     }
-    if (chk) {
-      {
-        ProfScope ps(k, 4, s);
-        hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts, ws.pwn, ws.pwd, ntw, M,
-                           (float)p->tol, OTLM_FP32_FLOOR, p->check_every, it, ws.ew_prev, ws.done, ws.iters,
-                           ws.status, ws.flags);
-      }
-      OTLM_HIP(hipGetLastError());
-      OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-      OTLM_HIP(hipStreamSynchronize(s));
-      if (ws.host_flags[0] == 0) break;
+  };
+  // One FP64 iteration (refinement phase, exact weight prox).
+  auto iterate64 = [&](int, bool chk) {
+    const int ntiles64 = (int)((np + G64_BN - 1) / G64_BN);
+    dim3 grid_n((unsigned)((np + G64_BN - 1) / G64_BN), (unsigned)((B + G64_BM - 1) / G64_BM));
+    {
+      ProfScope ps(k, 0, s);
+      GemmArgs64 g{ws.V64, (int)np, k->K64p, (int)np, M, (int)np, (int)np};
+      EpiSrc64 e{ws.S64, ws.A64, ws.U64, ws.psn, ws.psd, (int)np, (int)n, ntiles64, chk};
+      hipLaunchKernelGGL(gemm_nt_f64<EpiSrc64>, grid_n, dim3(256), 0, s, g, e);
     }
+    {
+      ProfScope ps(k, 1, s);
+      auto kern = prox_newton_kernel<double, double>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
+                         prox_newton_smem((int)n, sizeof(double)), s, prox_args64());
+    }
+    {
+      ProfScope ps(k, 2, s);
+      GemmArgs64 g{ws.W64, (int)kp, ws.Dp64, (int)kp, M, (int)np, (int)kp};
+      EpiUscale64 e{ws.A64, ws.U64, ws.S64, (int)np, (int)n, false};
+      hipLaunchKernelGGL(gemm_nt_f64<EpiUscale64>, grid_n, dim3(256), 0, s, g, e);
+    }
+    {
+      ProfScope ps(k, 3, s);
+      GemmArgs64 g{ws.U64, (int)np, k->KT64p, (int)np, M, (int)np, (int)np};
+      EpiProx64 e{ws.V64, Y, ws.done, pc64, (int)np, (int)n, (int)n, false};
+      hipLaunchKernelGGL(gemm_nt_f64<EpiProx64>, grid_n, dim3(256), 0, s, g, e);
+    }
+  };
+  // Runs one phase; returns the last iteration index or a negative status.
+  auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, int nts_phase) -> int {
+    int it = it0;
+    for (int j = 1; j <= cap; ++j) {
+      it = it0 + j;
+      const bool chk = (tol > 0.0) && (j % p->check_every == 0 || j == cap);
+      if (use64) iterate64(it, chk);
+      else iterate32(it, chk);
+      if (chk) {
+        {
+          ProfScope ps(k, 4, s);
+          hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts_phase, ws.pwn, ws.pwd,
+                             ntw, M, (float)tol, floor_w, p->check_every, it, ws.ew_prev, ws.ew_best, ws.stall,
+                             ws.done, ws.iters, ws.status, ws.flags);
+        }
+        if (hipGetLastError() != hipSuccess) return OTLM_E_HIP;
+        if (hipMemcpyAsync(ws.host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return OTLM_E_HIP;
+        if (ws.host_flags[0] == 0) break;
+      }
+    }
+    return hipGetLastError() == hipSuccess ? it : OTLM_E_HIP;
+  };
+
+  const bool refine = p->refine != OTLM_REFINE_NONE;
+  int last = run_phase(0, p->max_iter, refine ? p->bulk_tol : p->tol, OTLM_FP32_FLOOR, false, nts);
+  if (last < 0) return last;
+  bool state64 = false;
+  if (refine) {
+    hipLaunchKernelGGL(reopen_spectra, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, M, ws.done, ws.status,
+                       ws.ew_prev, ws.ew_best, ws.stall);
+    if (fp64) {
+      const size_t bn = (size_t)B * np;
+      hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.V, ws.V64, bn);
+      hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.U, ws.U64, bn);
+      hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.A, ws.A64, bn);
+      hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.W, ws.W64, (size_t)B * kp);
+      hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.Dp, ws.Dp64, (size_t)np * kp);
+      OTLM_HIP(hipGetLastError());
+      const int nts64 = (int)((np + G64_BN - 1) / G64_BN);
+      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, nts64);
+      state64 = true;
+    } else {
+      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, nts);
+    }
+    if (last < 0) return last;
   }
-  OTLM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
-                     ws.iters, (int)n, (int)kdim, (int)np, (int)kp, p->max_iter, W, logU, logV, iters, status);
+  if (state64)
+    hipLaunchKernelGGL(write_outputs64, dim3((unsigned)B), dim3(256), 0, s, ws.W64, ws.U64, ws.V64, ws.done,
+                       ws.status, ws.iters, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+  else
+    hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
+                       ws.iters, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   OTLM_HIP(hipGetLastError());
   return OTLM_OK;
 }

@@ -38,14 +38,16 @@ struct EpiSrc {
     const size_t o = (size_t)m * ld + n;
     if (n >= n_valid) {
       S[o] = 0.f;
-      R[o] = 0.f;
+      if (R) R[o] = 0.f;
       return;
     }
     const float a = A[o];
-    float r = 0.f;
-    if (a > 0.f) r = fminf(fmaxf(logf(s / a), -OTLM_R_CLAMP), OTLM_R_CLAMP);
     S[o] = s;
-    R[o] = r;
+    if (R) {
+      float r = 0.f;
+      if (a > 0.f) r = fminf(fmaxf(logf(s / a), -OTLM_R_CLAMP), OTLM_R_CLAMP);
+      R[o] = r;
+    }
     if (do_red) {
       red[0] += fabsf(U[o] * s - a);
       red[1] += a;
@@ -258,7 +260,8 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
                            const float* __restrict__ logVin, const float4* __restrict__ colc, int n, int k,
                            int np, int kp, int warm, float* __restrict__ V, float* __restrict__ W,
                            float* __restrict__ U, int* __restrict__ done, int* __restrict__ status,
-                           int* __restrict__ iters, float* __restrict__ ew_prev, int* __restrict__ bad) {
+                           int* __restrict__ iters, float* __restrict__ ew_prev, float* __restrict__ ew_best,
+                           int* __restrict__ stall, int* __restrict__ bad) {
   const int b = blockIdx.x;
   __shared__ double ssum[256];
   double acc = 0.0;
@@ -291,6 +294,8 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
     status[b] = 0;
     iters[b] = 0;
     ew_prev[b] = 0.f;
+    ew_best[b] = INFINITY;
+    stall[b] = 0;
   }
 }
 
@@ -301,11 +306,16 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
 // contraction rho = (e_w / e_w_prev)^(1/c) over the c iterations since the last
 // test, the distance to the limit is about e_w rho / (1 - rho).  A spectrum
 // stops when e_src <= tol and either that bound is <= tol or e_w has reached
-// the FP32 resolution `floor` (the iteration cannot move w any further).  One
-// workgroup; also counts the spectra still active into *active.
+// the resolution `floor` of the phase's precision (the iteration cannot move w
+// any further).  A spectrum whose e_w has not improved on its best value for
+// OTLM_STALL_CHECKS tests has reached the noise floor of its precision on an
+// ill-conditioned problem: it stops with status 8.  One workgroup; also counts
+// the spectra still active into *active.
+constexpr int OTLM_STALL_CHECKS = 6;
 __global__ void check_convergence(const float* __restrict__ psn, const float* __restrict__ psd, int nts,
                                   const float* __restrict__ pwn, const float* __restrict__ pwd, int ntw, int B,
                                   float tol, float floor_w, int c, int it, float* __restrict__ ew_prev,
+                                  float* __restrict__ ew_best, int* __restrict__ stall,
                                   int* __restrict__ done, int* __restrict__ iters, int* __restrict__ status,
                                   int* __restrict__ active) {
   __shared__ int cnt[1024];
@@ -332,13 +342,19 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
         const float rho = powf(ew / prev, 1.f / (float)c);
         bound = ew * rho / (1.f - rho);
       }
-      if (!isfinite(num + den + dw + wm)) {
+      int st = 0;
+      if (ew < ew_best[b]) {
+        ew_best[b] = ew;
+        stall[b] = 0;
+      } else {
+        stall[b] += 1;
+      }
+      if (!isfinite(num + den + dw + wm)) st = 4;
+      else if (esrc <= tol && (bound <= tol || ew <= floor_w)) st = 1;
+      else if (stall[b] >= OTLM_STALL_CHECKS) st = 8;
+      if (st) {
         done[b] = 1;
-        status[b] = 4;
-        iters[b] = it;
-      } else if (esrc <= tol && (bound <= tol || ew <= floor_w)) {
-        done[b] = 1;
-        status[b] = 1;
+        status[b] = st;
         iters[b] = it;
       } else {
         ++count;

@@ -17,8 +17,10 @@ LIB_PATH = os.path.join(HERE, "libotlm.so")
 FIT = {"balanced": 0, "kl": 1, "tv": 2, "l2": 3, "l2tv": 4, "poisson": 5}
 PEN = {"none": 0, "l1": 1, "l2sq": 2, "en": 3}
 PREC = {"fp32": 0, "bf16": 1}
+REFINE = {"none": 0, "fp32": 1, "fp64": 2}
+WSTEP = {"mm": 0, "exact": 1}
 
-STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE = 1, 2, 4
+STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED = 1, 2, 4, 8
 
 EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info",
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
@@ -33,9 +35,11 @@ class OtlmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("lambda_", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("bulk_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("fit", ctypes.c_int32),
-                ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("warm", ctypes.c_int32),
-                ("refine_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("refine_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32), ("wstep", ctypes.c_int32),
+                ("inner_max", ctypes.c_int32)]
 
 
 _lib = None
@@ -86,18 +90,24 @@ class SolveParams:
     tol: float = 1e-6
     max_iter: int = 1000
     check_every: int = 10
-    prec: str = "fp32"
+    prec: str = "fp32"          # bulk-phase products: "fp32" or "bf16"
+    refine: str = "none"        # refinement phase: "none", "fp32" or "fp64"
+    refine_sweeps: int = 200
+    bulk_tol: float = 1e-4
     warm: bool = False
-    refine_sweeps: int = 0
+    wstep: str = "mm"           # "mm" (one MM step, Algorithm 1) or "exact" (ProxP by Newton)
+    inner_max: int = 5
 
     def c(self) -> Params:
         p = Params()
         load().otlm_default_params(ctypes.byref(p))
         p.eps, p.lambda_, p.lambda2 = self.eps, self.lam, self.lam2
-        p.alpha, p.beta, p.tol = self.alpha, self.beta, self.tol
+        p.alpha, p.beta, p.tol, p.bulk_tol = self.alpha, self.beta, self.tol, self.bulk_tol
         p.max_iter, p.check_every = self.max_iter, self.check_every
         p.fit, p.pen, p.prec = FIT[self.fit], PEN[self.pen], PREC[self.prec]
-        p.warm, p.refine_sweeps = int(self.warm), self.refine_sweeps
+        p.refine, p.refine_sweeps = REFINE[self.refine], self.refine_sweeps
+        p.warm = int(self.warm)
+        p.wstep, p.inner_max = WSTEP[self.wstep], self.inner_max
         return p
 
 
