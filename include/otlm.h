@@ -189,16 +189,21 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
 
 /* Kernel timing on the solve's own stream.  While enabled, otlm_solve_batch
  * brackets every launch of its hot kernels with HIP events and accumulates
- * their durations per kernel class:
- *   [0] s = K v product (+ log-ratio epilogue)   [1] weight step (R D + MM map)
- *   [2] a = D w, u = a / s                        [3] t = K^T u product (+ prox)
+ * their durations per kernel class (9 classes):
+ *   [0] s = K v product, FP32 (+ log-ratio epilogue)
+ *   [1] weight step, FP32 state (MM GEMM epilogue or the Newton prox kernel)
+ *   [2] a = D w, u = a / s, FP32        [3] t = K^T u product + prox, FP32
  *   [4] convergence test
- * otlm_profile_read copies the mean duration in ms per launch (ms[5]) and the
- * launch counts (count[5]) accumulated since the last enable, synchronising
- * the recorded events first.  Enabling resets the counters.  Errors:
- * OTLM_E_INVALID for a null kernel. */
+ *   [5]..[8] the same as [0]..[3] in the FP64 refinement phase
+ * otlm_profile_read copies the mean duration in ms per launch (ms[9]) and the
+ * launch counts (count[9]) accumulated since the last enable, synchronising
+ * the recorded events first, and the Newton iterations the weight-prox
+ * kernels performed, summed over spectra (*newton_iters; a profiled solve
+ * synchronises its stream at the end to collect them).  Any output pointer
+ * may be NULL.  Enabling resets the counters.  Errors: OTLM_E_INVALID for a
+ * null kernel. */
 int otlm_profile_enable(otlm_kernel k, int32_t on);
-int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count);
+int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton_iters);
 
 /* Static description of an otlm_status code. */
 const char* otlm_status_str(int code);

@@ -50,6 +50,7 @@ struct Workspace {
   float* ew_prev = nullptr;
   float* ew_best = nullptr;
   int* stall = nullptr;
+  int* nit = nullptr;
   // FP64 refinement state
   int64_t B64 = 0;
   double *V64 = nullptr, *S64 = nullptr, *A64 = nullptr, *U64 = nullptr, *W64 = nullptr, *Dp64 = nullptr;
@@ -71,6 +72,7 @@ struct Workspace {
     ew_prev = nullptr;
     ew_best = nullptr;
     stall = nullptr;
+    nit = nullptr;
   }
   void release64() {
     for (void* p : allocs64) (void)hipFree(p);
@@ -93,7 +95,10 @@ struct Workspace {
 constexpr int OTLM_MM_WARMUP = 3;
 constexpr float OTLM_FP32_FLOOR = 4.76837158e-7f;  // 2^-21: weight changes below it are FP32 noise
 constexpr float OTLM_FP64_FLOOR = 1e-13f;          // the same for the FP64 state
-constexpr int MAX_TILES = 256;  // per-row partial slots: np / 64 <= 256 column tiles
+constexpr int MAX_TILES = 256;
+// kernel classes timed by otlm_profile_* (order documented in include/otlm.h)
+enum { PROF_KV32 = 0, PROF_W32, PROF_U32, PROF_KTU32, PROF_CHECK, PROF_KV64, PROF_W64, PROF_U64, PROF_KTU64,
+       OTLM_PROF_CLASSES };  // per-row partial slots: np / 64 <= 256 column tiles
 
 }  // namespace
 
@@ -112,10 +117,11 @@ struct otlm_kernel_s {
   Workspace ws;
   // kernel timing (otlm_profile_*)
   bool profile = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[OTLM_PROF_CLASSES];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  double prof_ms[OTLM_PROF_CLASSES] = {};
+  int64_t prof_n[OTLM_PROF_CLASSES] = {};
+  int64_t prof_newton = 0;  // Newton iterations of the weight-prox kernels (summed over spectra)
 };
 
 namespace {
@@ -156,6 +162,7 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.ew_prev, (size_t)B);
   rc |= dev_alloc(ws, &ws.ew_best, (size_t)B);
   rc |= dev_alloc(ws, &ws.stall, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nit, (size_t)B);
   if (rc != OTLM_OK) {
     ws.release();
     return OTLM_E_NOMEM;
@@ -209,7 +216,7 @@ struct ProfScope {
 
 // Fold recorded event pairs into the running means (synchronises the events).
 void prof_collect(otlm_kernel k) {
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     for (auto& e : k->ev[c]) {
       float ms = 0.f;
       if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
@@ -350,18 +357,20 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
 int otlm_profile_enable(otlm_kernel k, int32_t on) {
   if (!k) return OTLM_E_INVALID;
   prof_collect(k);
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     k->prof_ms[c] = 0.0;
     k->prof_n[c] = 0;
   }
+  k->prof_newton = 0;
   k->profile = on != 0;
   return OTLM_OK;
 }
 
-int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count) {
+int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton_iters) {
   if (!k) return OTLM_E_INVALID;
   prof_collect(k);
-  for (int c = 0; c < 5; ++c) {
+  if (newton_iters) *newton_iters = k->prof_newton;
+  for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     if (ms) ms[c] = k->prof_n[c] ? k->prof_ms[c] / (double)k->prof_n[c] : 0.0;
     if (count) count[c] = k->prof_n[c];
   }
@@ -434,6 +443,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
 
   OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
+  if (exact) OTLM_HIP(hipMemsetAsync(ws.nit, 0, (size_t)B * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
                      p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
@@ -474,6 +484,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
+    a.nit = ws.nit;
     return a;
   };
   auto prox_args64 = [&]() {
@@ -481,6 +492,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
+    a.nit = ws.nit;
     return a;
   };
 
@@ -488,30 +500,30 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   auto iterate32 = [&](int it, bool chk) {
     const bool mm_step = !exact || it <= OTLM_MM_WARMUP;
     {  // s = K v, r = log(s / a)
-      ProfScope ps(k, 0, s);
+      ProfScope ps(k, PROF_KV32, s);
       GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
       EpiSrc e{ws.S, mm_step ? ws.R : nullptr, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
       gemm(bm_k, bn_k, g, e, s);
     }
     if (!mm_step) {  // weight prox solved by active-set Newton
-      ProfScope ps(k, 1, s);
+      ProfScope ps(k, PROF_W32, s);
       auto kern = prox_newton_kernel<float, float>;
       hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
                          prox_newton_smem((int)n, sizeof(float)), s, prox_args32());
     } else {  // MM weight step
-      ProfScope ps(k, 1, s);
+      ProfScope ps(k, PROF_W32, s);
       GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
       EpiWupd e{ws.W, ws.colc, ws.done, ws.pwn, ws.pwd, (int)kp, (int)kdim, p->pen, ntw, chk};
       gemm(64, bn_w, g, e, s);
     }
     {  // a = D w, u = a / s
-      ProfScope ps(k, 2, s);
+      ProfScope ps(k, PROF_U32, s);
       GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
       EpiUscale e{ws.A, ws.U, ws.S, (int)np, (int)n, false};
       gemm(64, 128, g, e, s);
     }
     {  // t = K^T u, v = prox(t | y) / t
-      ProfScope ps(k, 3, s);
+      ProfScope ps(k, PROF_KTU32, s);
       GemmArgs g{ws.U, (int)np, k->KT, (int)np, M, (int)np, (int)np};
       EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false};
       gemm(bm_k, bn_k, g, e, s);
@@ -522,25 +534,25 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     const int ntiles64 = (int)((np + G64_BN - 1) / G64_BN);
     dim3 grid_n((unsigned)((np + G64_BN - 1) / G64_BN), (unsigned)((B + G64_BM - 1) / G64_BM));
     {
-      ProfScope ps(k, 0, s);
+      ProfScope ps(k, PROF_KV64, s);
       GemmArgs64 g{ws.V64, (int)np, k->K64p, (int)np, M, (int)np, (int)np};
       EpiSrc64 e{ws.S64, ws.A64, ws.U64, ws.psn, ws.psd, (int)np, (int)n, ntiles64, chk};
       hipLaunchKernelGGL(gemm_nt_f64<EpiSrc64>, grid_n, dim3(256), 0, s, g, e);
     }
     {
-      ProfScope ps(k, 1, s);
+      ProfScope ps(k, PROF_W64, s);
       auto kern = prox_newton_kernel<double, double>;
       hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
                          prox_newton_smem((int)n, sizeof(double)), s, prox_args64());
     }
     {
-      ProfScope ps(k, 2, s);
+      ProfScope ps(k, PROF_U64, s);
       GemmArgs64 g{ws.W64, (int)kp, ws.Dp64, (int)kp, M, (int)np, (int)kp};
       EpiUscale64 e{ws.A64, ws.U64, ws.S64, (int)np, (int)n, false};
       hipLaunchKernelGGL(gemm_nt_f64<EpiUscale64>, grid_n, dim3(256), 0, s, g, e);
     }
     {
-      ProfScope ps(k, 3, s);
+      ProfScope ps(k, PROF_KTU64, s);
       GemmArgs64 g{ws.U64, (int)np, k->KT64p, (int)np, M, (int)np, (int)np};
       EpiProx64 e{ws.V64, Y, ws.done, pc64, (int)np, (int)n, (int)n, false};
       hipLaunchKernelGGL(gemm_nt_f64<EpiProx64>, grid_n, dim3(256), 0, s, g, e);
@@ -556,7 +568,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       else iterate32(it, chk);
       if (chk) {
         {
-          ProfScope ps(k, 4, s);
+          ProfScope ps(k, PROF_CHECK, s);
           hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts_phase, ws.pwn, ws.pwd,
                              ntw, M, (float)tol, floor_w, p->check_every, it, ws.ew_prev, ws.ew_best, ws.stall,
                              ws.done, ws.iters, ws.status, ws.flags);
@@ -601,6 +613,12 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
                        ws.iters, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   OTLM_HIP(hipGetLastError());
+  if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
+    std::vector<int> h((size_t)B);
+    OTLM_HIP(hipMemcpyAsync(h.data(), ws.nit, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipStreamSynchronize(s));
+    for (int v : h) k->prof_newton += v;
+  }
   return OTLM_OK;
 }
 

@@ -39,6 +39,7 @@ struct ProxNewtonArgs {
   const int* done;
   float* pwn;          // e_w partials, one tile per spectrum
   float* pwd;
+  int* nit;            // Newton iterations done, accumulated per spectrum
   int ld_s, ld_w, ld_d, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
 };
@@ -127,7 +128,8 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   const double gscale = fmax(fmax(p.alpha, p.eps), 1e-300) * p.gtol;
   const double hpen = p.pen == PEN_L2SQ ? p.alpha : (p.pen == PEN_EN ? p.beta : 0.0);
 
-  for (int it = 0; it < p.max_newton; ++it) {
+  int it = 0;
+  for (; it < p.max_newton; ++it) {
     const double f = pn_eval(p, w, s, a, red);   // also a = D w
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
     for (int i = tid; i < n; i += PN_THREADS) l[i] = log(fmax(a[i], tiny) / (double)s[i]);
@@ -305,6 +307,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   if (tid == 0) {
     p.pwn[b] = (float)dw;
     p.pwd[b] = (float)wm;
+    p.nit[b] += it;
   }
 }
 

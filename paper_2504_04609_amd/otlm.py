@@ -25,7 +25,8 @@ STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED = 1, 2, 4,
 EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info",
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
             "otlm_profile_read")
-PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test")
+PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
+                   "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64")
 
 
 class OtlmError(RuntimeError):
@@ -62,7 +63,7 @@ def load() -> ctypes.CDLL:
     lib.otlm_solve_batch.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(Params), vp, vp, vp, vp, vp, vp]
     lib.otlm_objective.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.POINTER(Params), vp, vp, vp, vp, vp]
     lib.otlm_profile_enable.argtypes = [vp, ctypes.c_int32]
-    lib.otlm_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    lib.otlm_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.otlm_status_str.argtypes = [ctypes.c_int]
     lib.otlm_status_str.restype = ctypes.c_char_p
     for name in ("otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info", "otlm_solve_batch", "otlm_objective",
@@ -153,10 +154,13 @@ class GibbsKernel:
 
     def profile_read(self):
         """Mean ms per launch and launch count for each timed kernel class."""
-        ms = (ctypes.c_double * 5)()
-        cnt = (ctypes.c_int64 * 5)()
-        _check(load().otlm_profile_read(self.handle, ms, cnt), "otlm_profile_read")
-        return {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_CLASSES)}
+        ms = (ctypes.c_double * len(PROFILE_CLASSES))()
+        cnt = (ctypes.c_int64 * len(PROFILE_CLASSES))()
+        nit = ctypes.c_int64()
+        _check(load().otlm_profile_read(self.handle, ms, cnt, ctypes.byref(nit)), "otlm_profile_read")
+        out = {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_CLASSES)}
+        out["newton_iters"] = nit.value
+        return out
 
     def close(self):
         if getattr(self, "handle", None):
