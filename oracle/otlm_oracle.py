@@ -248,8 +248,13 @@ def prox_P_exact(s, D, w0, pen: str, eps: float, alpha: float, beta: float = 0.0
         t = min(1.0, tmax)
         slope = float(g[F] @ d)
         accepted = False
-        if slope < 0:
-            while t >= 1e-18:
+        if slope < 0 and -slope <= 1e-14 * abs(f):
+            # predicted decrease below the FP64 resolution of V: take the step untested
+            wn = w.copy()
+            wn[F] = np.maximum(w[F] + t * d, 0.0)
+            accepted = True
+        elif slope < 0:
+            for _ in range(30):
                 wn = w.copy()
                 wn[F] = np.maximum(w[F] + t * d, 0.0)
                 fn = V(wn)

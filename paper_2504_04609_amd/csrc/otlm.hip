@@ -93,6 +93,12 @@ struct Workspace {
 // cold start s = K 1 carries far more mass than y and an exact prox there
 // drives weights to scales that Newton leaves only slowly.
 constexpr int OTLM_MM_WARMUP = 3;
+// Scaled gradient tolerance of the Newton weight prox during an FP32 bulk phase
+// that an FP64 refinement will follow (the outer iterate is itself only good to
+// ~1e-5 there); the FP64 phase and FP32-only solves use 1e-13.
+#ifndef OTLM_BULK_GTOL
+#define OTLM_BULK_GTOL 1e-9
+#endif
 constexpr float OTLM_FP32_FLOOR = 4.76837158e-7f;  // 2^-21: weight changes below it are FP32 noise
 constexpr float OTLM_FP64_FLOOR = 1e-13f;          // the same for the FP64 state
 constexpr int MAX_TILES = 256;
@@ -481,15 +487,16 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
 
   auto prox_args32 = [&]() {
     ProxNewtonArgs<float, float> a;
-    a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
-    a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
+    a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
+    a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
     a.nit = ws.nit;
     return a;
   };
   auto prox_args64 = [&]() {
     ProxNewtonArgs<double, double> a;
-    a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit;

@@ -11,36 +11,40 @@
 //   Hessian   H = alpha R'' + eps D^T diag(1 / D w) D          (free weights only)
 // Newton step on the free weights, ratio test to the first weight reaching 0
 // (it joins the active set), Armijo backtracking, and release of the active
-// weight with the most negative gradient once the free gradient vanishes.
-// Weights that are exactly 0 are the active set, so the state carried between
-// outer iterations is just W.
+// weight with the most negative gradient once the free gradient is small next
+// to it.  Weights that are exactly 0 are the active set, so the state carried
+// between outer iterations is just W.
 //
-// One workgroup (256 threads) per spectrum, everything in FP64 (the Hessian of
-// an overlapping Gaussian dictionary has condition numbers near 1e12).  LDS
-// holds s, a = D w and 1/sqrt(a) or log(a/s) for the n bins, the 64 x 64
-// Hessian / Cholesky factor and an 8-bin slab of scaled dictionary rows:
-// (16 + sizeof(s)) n + 39.5 KB, so n <= 1024 fits the 64 KB a workgroup gets
-// by default in both the FP32-state and the FP64-state (refinement) variants.
+// One workgroup (256 threads, 4 wave64s) per spectrum, everything in FP64 (the
+// Hessian of an overlapping Gaussian dictionary has condition numbers near
+// 1e12).  LDS holds s, a = D w and log(a/s) or 1/sqrt(a) for the n bins and the
+// 64 x 64 Hessian: (16 + sizeof(s)) n + 35 KB, so n <= 1024 fits in 64 KB.
+// The dictionary is streamed from L2 with many independent loads in flight
+// (D^T for the bin sweeps, D for the column sweeps).  The Hessian is built with
+// 8 x 4 register blocks per thread over two bin groups; the Cholesky
+// factorisation runs by 16 x 16 tiles and the two triangular solves in one wave,
+// one row per lane.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "solver_kernels.hpp"
 
 constexpr int PN_THREADS = 256;
 constexpr int PN_K = 64;    // largest dictionary handled by this kernel
-constexpr int PN_CH = 8;    // bins per slab in the Hessian build
 constexpr int PN_HLD = PN_K + 1;
+constexpr int PN_MAXB = 4;  // bins per thread in bin sweeps: n <= 1024
 
 template <class TS, class TW>
 struct ProxNewtonArgs {
   const TS* S;         // [B, ld_s]  s = K v
   TW* W;               // [B, ld_w]  weights (in: start, out: prox)
   const float* Dp;     // [np, ld_d] dictionary, zero padded
+  const float* DTp;    // [kp, ld_dt] its transpose (coalesced column sweeps)
   const float4* colc;  // per column {1/x_j, ...}
   const int* done;
   float* pwn;          // e_w partials, one tile per spectrum
   float* pwd;
   int* nit;            // Newton iterations done, accumulated per spectrum
-  int ld_s, ld_w, ld_d, n, k, pen, max_newton;
+  int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
 };
 
@@ -62,6 +66,12 @@ __device__ __forceinline__ double pn_block_min(double v, double* red) {
   return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
+// Wave-local synchronisation for LDS traffic among the lanes of one wave.
+__device__ __forceinline__ void pn_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // penalty value alpha R(w) and derivatives, per weight
 __device__ __forceinline__ double pn_pen(int pen, double w, double alpha, double beta) {
   if (pen == PEN_L1) return alpha * w;
@@ -77,18 +87,46 @@ __device__ __forceinline__ double pn_pen_grad(int pen, double w, double alpha, d
 }
 
 // V(w) = eps sum_i (a_i log(a_i/s_i) - a_i + s_i) + sum_j alpha R(w_j), a = D w
-// (bins with a = 0 give s_i); stores a when `a` is not null.
+// (bins with a = 0 give s_i); stores a when `a` is not null.  Each thread owns
+// up to PN_MAXB bins and keeps their sums independent so the D^T loads overlap.
 template <class TS, class TW>
 __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const double* w, const TS* s, double* a, double* red) {
   const int n = p.n, k = p.k;
+  double ai[PN_MAXB];
+#pragma unroll
+  for (int q = 0; q < PN_MAXB; ++q) ai[q] = 0.0;
+  const float* base = p.DTp + threadIdx.x;
+  const int nq = (n - (int)threadIdx.x + PN_THREADS - 1) / PN_THREADS;  // bins of this thread
+  int j = 0;
+  for (; j + 7 < k; j += 8) {  // eight columns per step: up to 32 independent loads in flight
+    float dv[8][PN_MAXB];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < PN_MAXB; ++q)
+        dv[u][q] = q < nq ? base[(size_t)(j + u) * p.ld_dt + q * PN_THREADS] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double wj = w[j + u];
+#pragma unroll
+      for (int q = 0; q < PN_MAXB; ++q) ai[q] += (double)dv[u][q] * wj;
+    }
+  }
+  for (; j < k; ++j) {
+    const double wj = w[j];
+#pragma unroll
+    for (int q = 0; q < PN_MAXB; ++q)
+      if (q < nq) ai[q] += (double)base[(size_t)j * p.ld_dt + q * PN_THREADS] * wj;
+  }
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += PN_THREADS) {
-    const float* drow = p.Dp + (size_t)i * p.ld_d;
-    double ai = 0.0;
-    for (int j = 0; j < k; ++j) ai += (double)drow[j] * w[j];
-    if (a) a[i] = ai;
-    const double si = (double)s[i];
-    acc += (ai > 0.0 ? ai * log(ai / si) : 0.0) - ai + si;
+#pragma unroll
+  for (int q = 0; q < PN_MAXB; ++q) {
+    const int i = threadIdx.x + q * PN_THREADS;
+    if (i < n) {
+      if (a) a[i] = ai[q];
+      const double si = (double)s[i];
+      acc += (ai[q] > 0.0 ? ai[q] * log(ai[q] / si) : 0.0) - ai[q] + si;
+    }
   }
   double v = p.eps * pn_block_sum(acc, red);
   double pv = 0.0;
@@ -101,16 +139,16 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   const int b = blockIdx.x;
   if (p.done[b]) return;
   extern __shared__ double smem[];
-  const int n = p.n, k = p.k, tid = threadIdx.x;
+  const int n = p.n, k = p.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* a = smem;                    // [n]  D w at the current point
   double* l = a + n;                   // [n]  log(a/s) or 1/sqrt(a)
   double* H = l + n;                   // [64][65]
-  double* Ms = H + PN_K * PN_HLD;      // [PN_CH][64]
-  double* w = Ms + PN_CH * PN_K;       // [64]
+  double* w = H + PN_K * PN_HLD;       // [64]
   double* wt = w + PN_K;               // [64]
   double* g = wt + PN_K;               // [64]
   double* d = g + PN_K;                // [64]
-  double* red = d + PN_K;              // [8]
+  double* gp = d + PN_K;               // [4][64] gradient partials
+  double* red = gp + 4 * PN_K;         // [8]
   TS* s = reinterpret_cast<TS*>(red + 8);  // [n]
   __shared__ int act[PN_K];
   __shared__ int ctl[4];
@@ -130,19 +168,30 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
 
   int it = 0;
   for (; it < p.max_newton; ++it) {
-    const double f = pn_eval(p, w, s, a, red);   // also a = D w
+    const double f = pn_eval(p, w, s, a, red);   // also a = D w (block_sum synchronises)
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
     for (int i = tid; i < n; i += PN_THREADS) l[i] = log(fmax(a[i], tiny) / (double)s[i]);
     __syncthreads();
     {
-      const int j = tid & 63, q = tid >> 6;
-      double part = 0.0;
-      if (j < k)
-        for (int i = q; i < n; i += 4) part += (double)p.Dp[(size_t)i * p.ld_d + j] * l[i];
-      Ms[q * PN_K + j] = part;
+      // thread (j = lane, q = wave) sums bins i = q, q + 4, ... of column j;
+      // eight independent partial sums keep the D loads in flight
+      const int j = lane, q = wave;
+      double part[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) part[u] = 0.0;
+      if (j < k) {
+        const float* dcol = p.Dp + j;
+        int i = q;
+        for (; i + 28 < n; i += 32) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * p.ld_d] * l[i + 4 * u];
+        }
+        for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * p.ld_d] * l[i];
+      }
+      gp[q * PN_K + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
       __syncthreads();
       if (tid < PN_K) {
-        const double gj = Ms[tid] + Ms[PN_K + tid] + Ms[2 * PN_K + tid] + Ms[3 * PN_K + tid];
+        const double gj = (gp[tid] + gp[PN_K + tid]) + (gp[2 * PN_K + tid] + gp[3 * PN_K + tid]);
         g[tid] = tid < k ? pn_pen_grad(p.pen, w[tid], p.alpha, p.beta) + p.eps * gj : 0.0;
       }
       __syncthreads();
@@ -158,60 +207,60 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
           jmin = j;
         }
       }
-      int stop = 0;
-      if (kkt <= gscale) {
-        if (jmin >= 0 && gmin < -gscale) act[jmin] = 0;
-        else stop = 1;
+      int stop = 0, released = -1;
+      if (kkt <= gscale && !(jmin >= 0 && gmin < -gscale)) stop = 1;
+      else if (jmin >= 0 && gmin < -gscale && kkt <= fmax(gscale, 0.1 * fabs(gmin))) {
+        act[jmin] = 0;
+        released = jmin;
+        jmin = -1;
       }
       ctl[0] = stop;
+      ctl[1] = released;
+      ctl[2] = (jmin >= 0 && gmin < -gscale) ? jmin : -1;   // release candidate if no descent is left
     }
     __syncthreads();
     if (ctl[0]) break;
+    const int released = ctl[1];
 
     // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
-    for (int i = tid; i < n; i += PN_THREADS) l[i] = 1.0 / sqrt(fmax(a[i], tiny));
+    for (int i = tid; i < n; i += PN_THREADS) l[i] = 1.0 / fmax(a[i], tiny);
+    __syncthreads();
     {
-      const int q = tid >> 6, blk = tid & 63, bj = blk >> 3, bl = blk & 7;
-      double acc[8][8];
+      // 128 register blocks of 8 x 4 entries (block row bj = 0..7, block column
+      // bl = 0..15) over two bin groups (bins of parity q)
+      const int q = tid >> 7, blk = tid & 127, bj = blk >> 4, bl = blk & 15;
+      double acc[8][4];
 #pragma unroll
       for (int x = 0; x < 8; ++x)
 #pragma unroll
-        for (int y = 0; y < 8; ++y) acc[x][y] = 0.0;
-      for (int c0 = 0; c0 < n; c0 += PN_CH) {
-        __syncthreads();
-        for (int e = tid; e < PN_CH * PN_K; e += PN_THREADS) {
-          const int r = e >> 6, j = e & 63, i = c0 + r;
-          Ms[e] = (i < n && j < k) ? (double)p.Dp[(size_t)i * p.ld_d + j] * l[i] : 0.0;
-        }
-        __syncthreads();
-        for (int r = q; r < PN_CH; r += 4) {
-          const double* row = Ms + r * PN_K;
-          double xa[8], xb[8];
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+      const float* rowj = p.Dp + bj * 8;
+      const float* rowl = p.Dp + bl * 4;
+      for (int i = q; i < n; i += 2) {
+        const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * p.ld_d);
+        const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * p.ld_d + 4);
+        const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * p.ld_d);
+        const double sc = l[i];  // 1 / a_i
+        const double xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
+        const double xb[4] = {(double)lv.x, (double)lv.y, (double)lv.z, (double)lv.w};
 #pragma unroll
-          for (int x = 0; x < 8; ++x) {
-            xa[x] = row[bj * 8 + x];
-            xb[x] = row[bl * 8 + x];
-          }
+        for (int x = 0; x < 8; ++x)
 #pragma unroll
-          for (int x = 0; x < 8; ++x)
-#pragma unroll
-            for (int y = 0; y < 8; ++y) acc[x][y] += xa[x] * xb[y];
-        }
+          for (int y = 0; y < 4; ++y) acc[x][y] += xa[x] * xb[y];
       }
-      // fold the four bin groups into H (sequentially, one group at a time)
-      for (int grp = 0; grp < 4; ++grp) {
-        __syncthreads();
+      // fold the two bin groups into H
+      for (int grp = 0; grp < 2; ++grp) {
         if (q == grp) {
 #pragma unroll
           for (int x = 0; x < 8; ++x)
 #pragma unroll
-            for (int y = 0; y < 8; ++y) {
-              double* h = &H[(bj * 8 + x) * PN_HLD + bl * 8 + y];
+            for (int y = 0; y < 4; ++y) {
+              double* h = &H[(bj * 8 + x) * PN_HLD + bl * 4 + y];
               *h = (grp == 0 ? 0.0 : *h) + acc[x][y];
             }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
     // scale, add the penalty curvature, and pin the active weights (identity rows)
     for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) {
@@ -222,38 +271,84 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       H[r * PN_HLD + c] = h;
     }
     __syncthreads();
-    // ---- Cholesky H = L L^T (lower triangle, in place)
-    for (int c = 0; c < PN_K; ++c) {
-      if (tid == 0) {
-        const double dgl = H[c * PN_HLD + c];
-        H[c * PN_HLD + c] = sqrt(dgl > 0.0 ? dgl : 1e-300);
-      }
-      __syncthreads();
-      const double piv = H[c * PN_HLD + c];
-      for (int r = c + 1 + tid; r < PN_K; r += PN_THREADS) H[r * PN_HLD + c] /= piv;
-      __syncthreads();
-      const int m = PN_K - 1 - c;
-      for (int e = tid; e < m * m; e += PN_THREADS) {
-        const int r = c + 1 + e / m, cc = c + 1 + e % m;
-        if (cc <= r) H[r * PN_HLD + cc] -= H[r * PN_HLD + c] * H[cc * PN_HLD + c];
-      }
-      __syncthreads();
-    }
-    // ---- solve L L^T d = -g (active rows have g = 0 -> d = 0)
-    if (tid < PN_K) d[tid] = act[tid] ? 0.0 : -g[tid];
+    const double hrel_diag = released >= 0 ? H[released * PN_HLD + released] : 1.0;
     __syncthreads();
-    for (int c = 0; c < PN_K; ++c) {  // forward: L y = -g
-      if (tid == 0) d[c] /= H[c * PN_HLD + c];
+
+    // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
+    // the diagonal tile in one wave, solve the panel below it (one thread per
+    // row), update the trailing lower triangle (all threads), four rounds.
+    for (int kk = 0; kk < PN_K; kk += 16) {
+      if (wave == 0 && lane < 16) {
+        const int r = kk + lane;
+        double* Hr = H + r * PN_HLD;
+        for (int c = kk; c < kk + 16; ++c) {
+          double acc = 0.0;
+          if (r >= c) {
+            const double* Hc = H + c * PN_HLD;
+            acc = Hr[c];
+            for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
+          }
+          if (r == c) Hr[c] = sqrt(acc > 0.0 ? acc : 1e-300);
+          pn_wave_sync();
+          if (r > c) Hr[c] = acc / H[c * PN_HLD + c];
+          pn_wave_sync();
+        }
+      }
       __syncthreads();
-      for (int r = c + 1 + tid; r < PN_K; r += PN_THREADS) d[r] -= H[r * PN_HLD + c] * d[c];
+      for (int r = kk + 16 + tid; r < PN_K; r += PN_THREADS) {
+        double* Hr = H + r * PN_HLD;
+        for (int c = kk; c < kk + 16; ++c) {
+          const double* Hc = H + c * PN_HLD;
+          double acc = Hr[c];
+          for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
+          Hr[c] = acc / Hc[c];
+        }
+      }
+      __syncthreads();
+      const int m = PN_K - kk - 16;
+      for (int e = tid; e < m * m; e += PN_THREADS) {
+        const int r = kk + 16 + e / m, c = kk + 16 + e % m;
+        if (c <= r) {
+          const double* Hr = H + r * PN_HLD;
+          const double* Hc = H + c * PN_HLD;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; q += 2) {
+            s0 += Hr[kk + q] * Hc[kk + q];
+            s1 += Hr[kk + q + 1] * Hc[kk + q + 1];
+          }
+          H[r * PN_HLD + c] -= s0 + s1;
+        }
+      }
       __syncthreads();
     }
-    for (int c = PN_K - 1; c >= 0; --c) {  // backward: L^T d = y
-      if (tid == 0) d[c] /= H[c * PN_HLD + c];
-      __syncthreads();
-      for (int r = tid; r < c; r += PN_THREADS) d[r] -= H[c * PN_HLD + r] * d[c];
-      __syncthreads();
+
+    // ---- solve L L^T d = -g in wave 0 (lane r owns row r)
+    if (wave == 0) {
+      const int r = lane;
+      const double hdiag_released = released >= 0 ? hrel_diag : 1.0;
+      const double* Hr = H + r * PN_HLD;
+      // forward: L y = -g ; backward: L^T d = y   (active rows: g = 0, L row = e_r)
+      double y = act[r] ? 0.0 : -g[r];
+      for (int c = 0; c < PN_K; ++c) {
+        const double yc = __shfl(y, c, 64) / H[c * PN_HLD + c];
+        if (r == c) y = yc;
+        else if (r > c) y -= Hr[c] * yc;
+      }
+      for (int c = PN_K - 1; c >= 0; --c) {
+        const double dc = __shfl(y, c, 64) / H[c * PN_HLD + c];
+        if (r == c) y = dc;
+        else if (r < c) y -= H[c * PN_HLD + r] * dc;
+      }
+      // weights at 0 cannot decrease; a released weight swamped by the coupling
+      // takes its own Newton coordinate step instead
+      if (w[r] <= 0.0 && y < 0.0) y = 0.0;
+      const double yr = __shfl(y, released >= 0 ? released : 0, 64);
+      if (released >= 0 && yr <= 0.0) y = (r == released) ? -g[r] / hdiag_released : 0.0;
+      d[r] = act[r] ? 0.0 : y;
     }
+    __syncthreads();
+
     // ---- ratio test and Armijo backtracking
     double slope = 0.0, tmax = INFINITY;
     {
@@ -262,20 +357,36 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       slope = pn_block_sum(sl, red);
       tmax = pn_block_min(tm, red);
     }
-    if (!(slope < 0.0)) break;
-    double t = fmin(1.0, tmax), fn = 0.0;
     bool accepted = false;
-    for (int ls = 0; ls < 60; ++ls) {
+    double t = fmin(1.0, tmax);
+    if (slope < 0.0 && -slope <= 1e-14 * fabs(f)) {
+      // the predicted decrease is below what V can resolve in FP64: the point is
+      // optimal to working precision on this free set, take the step untested
       if (tid < PN_K) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
       __syncthreads();
-      fn = pn_eval(p, wt, s, nullptr, red);
-      if (fn <= f + 1e-4 * t * slope) {
-        accepted = true;
-        break;
+      accepted = true;
+    } else if (slope < 0.0) {
+      for (int ls = 0; ls < 30; ++ls) {
+        if (tid < PN_K) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
+        __syncthreads();
+        const double fn = pn_eval(p, wt, s, nullptr, red);
+        if (fn <= f + 1e-4 * t * slope) {
+          accepted = true;
+          break;
+        }
+        t *= 0.5;
       }
-      t *= 0.5;
     }
-    if (!accepted) break;
+    if (!accepted) {  // no descent left on this free set: release the candidate, or stop
+      const int cand = ctl[2];
+      __syncthreads();
+      if (cand >= 0) {
+        if (tid == 0) act[cand] = 0;
+        __syncthreads();
+        continue;
+      }
+      break;
+    }
     const bool hit = (t == tmax);
     if (tid < PN_K) {
       double wn = wt[tid];
@@ -312,5 +423,5 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
 }
 
 inline size_t prox_newton_smem(int n, size_t s_bytes) {
-  return sizeof(double) * ((size_t)2 * n + PN_K * PN_HLD + PN_CH * PN_K + 4 * PN_K + 8) + s_bytes * (size_t)n;
+  return sizeof(double) * ((size_t)2 * n + PN_K * PN_HLD + 8 * PN_K + 8) + s_bytes * (size_t)n;
 }
