@@ -17,6 +17,7 @@ Arms (all cold start, all through the C-ABI):
                  300 iterations (it does not converge on this l1 workload)
   exact_fp32     weight prox solved exactly per iteration (Newton), FP32 state
   exact_fp32_64  the same with an FP64 refinement phase (headline)
+  exact_bf16_64  BF16 kernel products in the bulk phase, then the FP64 refinement
 
 Prints one JSON line; the roofline entry is the kernel class with the largest
 total time in the headline arm, timed with HIP events on the solve's stream
@@ -36,7 +37,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6}  # TFLOP/s, MI355X
+PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6, "bf16_mfma": 2500.0}  # TFLOP/s, MI355X
 
 
 def kernel_nonzero_fraction(C, eps):
@@ -54,6 +55,9 @@ def arm_params(name, wl, otlm):
     if name == "exact_fp32_64":
         return otlm.SolveParams(**base, tol=1e-9, bulk_tol=1e-4, max_iter=400, wstep="exact", inner_max=5,
                                 refine="fp64", refine_sweeps=200)
+    if name == "exact_bf16_64":
+        return otlm.SolveParams(**base, tol=1e-9, bulk_tol=1e-3, max_iter=400, wstep="exact", inner_max=5,
+                                prec="bf16", refine="fp64", refine_sweeps=300)
     raise ValueError(name)
 
 
@@ -63,9 +67,10 @@ def roofline(prof, B, n, k, phi):
     dom = max(totals, key=totals.get)
     ms, cnt = prof[dom]
     entry = {"kernel": dom, "ms_per_launch": ms, "launches": cnt, "traffic": None}
-    if dom in ("kv_product", "ktu_product", "kv_product_f64", "ktu_product_f64"):
+    if dom in ("kv_product", "ktu_product", "kv_product_f64", "ktu_product_f64", "kv_product_bf16",
+               "ktu_product_bf16"):
         flops = 2.0 * B * n * n * phi
-        peak = PEAK["fp64_mfma"] if dom.endswith("f64") else PEAK["fp32_mfma"]
+        peak = {"f64": PEAK["fp64_mfma"], "bf16": PEAK["bf16_mfma"]}.get(dom.rsplit("_", 1)[-1], PEAK["fp32_mfma"])
         entry.update(bound="mfma", unit="TFLOP/s", peak=peak, flops_per_launch=flops)
     elif dom in ("weight_step", "weight_prox_f64") and prof["newton_iters"] > 0:
         # FP64 Newton on the weight prox: per Newton iteration and spectrum the
@@ -89,7 +94,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sample", type=int, default=8)
-    ap.add_argument("--arms", default="paper_mm,exact_fp32,exact_fp32_64")
+    ap.add_argument("--arms", default="paper_mm,exact_fp32,exact_bf16_64,exact_fp32_64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -165,7 +165,8 @@ int otlm_kernel_info(otlm_kernel k, int64_t* n, int32_t* symmetric, double* eps)
  * kernel's, 1 <= kdim <= 256, B >= 0; negative or non-finite D or Y, or a D
  * column summing to 0), OTLM_E_UNSUPPORTED (WSTEP_EXACT beyond its sizes,
  * REFINE_FP64 without WSTEP_EXACT), OTLM_E_NOMEM, OTLM_E_HIP.  B = 0 is a
- * no-op. */
+ * no-op.  A BF16 bulk phase keeps the state in FP32 and rounds only the
+ * operands of the two kernel products (v, u and K) to BF16. */
 int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y, int64_t B,
                      const otlm_params* p, float* W, float* logU, float* logV,
                      int32_t* iters, int32_t* status, void* stream);
@@ -189,14 +190,15 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
 
 /* Kernel timing on the solve's own stream.  While enabled, otlm_solve_batch
  * brackets every launch of its hot kernels with HIP events and accumulates
- * their durations per kernel class (9 classes):
+ * their durations per kernel class (11 classes):
  *   [0] s = K v product, FP32 (+ log-ratio epilogue)
  *   [1] weight step, FP32 state (MM GEMM epilogue or the Newton prox kernel)
  *   [2] a = D w, u = a / s, FP32        [3] t = K^T u product + prox, FP32
  *   [4] convergence test
  *   [5]..[8] the same as [0]..[3] in the FP64 refinement phase
- * otlm_profile_read copies the mean duration in ms per launch (ms[9]) and the
- * launch counts (count[9]) accumulated since the last enable, synchronising
+ *   [9] s = K v product in BF16 (FP32 accumulate)  [10] t = K^T u in BF16
+ * otlm_profile_read copies the mean duration in ms per launch (ms[11]) and the
+ * launch counts (count[11]) accumulated since the last enable, synchronising
  * the recorded events first, and the Newton iterations the weight-prox
  * kernels performed, summed over spectra (*newton_iters; a profiled solve
  * synchronises its stream at the end to collect them).  Any output pointer

@@ -22,6 +22,7 @@
 #include "../../include/otlm.h"
 #include "gemm_nt.hpp"
 #include "gemm_nt_f64.hpp"
+#include "gemm_nt_bf16.hpp"
 #include "objective_kernels.hpp"
 #include "prox_newton.hpp"
 #include "solver_kernels.hpp"
@@ -51,6 +52,7 @@ struct Workspace {
   float* ew_best = nullptr;
   int* stall = nullptr;
   int* nit = nullptr;
+  unsigned short *Vbf = nullptr, *Ubf = nullptr;
   // FP64 refinement state
   int64_t B64 = 0;
   double *V64 = nullptr, *S64 = nullptr, *A64 = nullptr, *U64 = nullptr, *W64 = nullptr, *Dp64 = nullptr;
@@ -73,6 +75,7 @@ struct Workspace {
     ew_best = nullptr;
     stall = nullptr;
     nit = nullptr;
+    Vbf = Ubf = nullptr;
   }
   void release64() {
     for (void* p : allocs64) (void)hipFree(p);
@@ -101,10 +104,11 @@ constexpr int OTLM_MM_WARMUP = 3;
 #endif
 constexpr float OTLM_FP32_FLOOR = 4.76837158e-7f;  // 2^-21: weight changes below it are FP32 noise
 constexpr float OTLM_FP64_FLOOR = 1e-13f;          // the same for the FP64 state
+constexpr float OTLM_BF16_FLOOR = 3.0e-4f;         // ~2^-12: BF16 products move w by about this much
 constexpr int MAX_TILES = 256;
 // kernel classes timed by otlm_profile_* (order documented in include/otlm.h)
 enum { PROF_KV32 = 0, PROF_W32, PROF_U32, PROF_KTU32, PROF_CHECK, PROF_KV64, PROF_W64, PROF_U64, PROF_KTU64,
-       OTLM_PROF_CLASSES };  // per-row partial slots: np / 64 <= 256 column tiles
+       PROF_KVBF, PROF_KTUBF, OTLM_PROF_CLASSES };  // per-row partial slots: np / 64 <= 256 column tiles
 
 }  // namespace
 
@@ -118,6 +122,8 @@ struct otlm_kernel_s {
   double* K64 = nullptr;  // [n, n] FP64
   double* KT64 = nullptr; // == K64 when symmetric
   double* K64p = nullptr;  // [np, np] FP64, zero padded (refinement products)
+  unsigned short* Kbf = nullptr;   // [np, np] BF16 (bulk-phase products)
+  unsigned short* KTbf = nullptr;  // == Kbf when symmetric
   double* KT64p = nullptr; // == K64p when symmetric
   double sumK = 0.0;
   Workspace ws;
@@ -169,6 +175,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.ew_best, (size_t)B);
   rc |= dev_alloc(ws, &ws.stall, (size_t)B);
   rc |= dev_alloc(ws, &ws.nit, (size_t)B);
+  rc |= dev_alloc(ws, &ws.Vbf, bn);
+  rc |= dev_alloc(ws, &ws.Ubf, bn);
   if (rc != OTLM_OK) {
     ws.release();
     return OTLM_E_NOMEM;
@@ -321,7 +329,8 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
   const size_t npp = (size_t)k->np * k->np;
   if (hipMalloc(&k->K, npp * sizeof(float)) != hipSuccess ||
       hipMalloc(&k->K64, (size_t)n * n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&k->K64p, npp * sizeof(double)) != hipSuccess) {
+      hipMalloc(&k->K64p, npp * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->Kbf, npp * sizeof(unsigned short)) != hipSuccess) {
     otlm_free_kernel(k);
     return OTLM_E_NOMEM;
   }
@@ -329,9 +338,11 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
     k->KT = k->K;
     k->KT64 = k->K64;
     k->KT64p = k->K64p;
+    k->KTbf = k->Kbf;
   } else if (hipMalloc(&k->KT, npp * sizeof(float)) != hipSuccess ||
              hipMalloc(&k->KT64, (size_t)n * n * sizeof(double)) != hipSuccess ||
-             hipMalloc(&k->KT64p, npp * sizeof(double)) != hipSuccess) {
+             hipMalloc(&k->KT64p, npp * sizeof(double)) != hipSuccess ||
+             hipMalloc(&k->KTbf, npp * sizeof(unsigned short)) != hipSuccess) {
     otlm_free_kernel(k);
     return OTLM_E_NOMEM;
   }
@@ -340,10 +351,12 @@ int otlm_make_kernel(const double* C, int64_t n, double eps, void* stream, otlm_
   hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->K);
   hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 0, k->K64);
   hipLaunchKernelGGL(build_kernel_f64p, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->K64p);
+  hipLaunchKernelGGL(build_kernel_bf16, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 0, k->Kbf);
   if (!sym) {
     hipLaunchKernelGGL(build_kernel_f32, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KT);
     hipLaunchKernelGGL(build_kernel_f64, g64, dim3(256), 0, s, C, (int)n, inv, 1, k->KT64);
     hipLaunchKernelGGL(build_kernel_f64p, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KT64p);
+    hipLaunchKernelGGL(build_kernel_bf16, g32, dim3(256), 0, s, C, (int)n, (int)k->np, inv, 1, k->KTbf);
   }
   if (hipGetLastError() != hipSuccess) {
     otlm_free_kernel(k);
@@ -395,6 +408,8 @@ int otlm_free_kernel(otlm_kernel k) {
   k->ws.release64();
   k->ws.release_obj();
   if (k->KT64p && k->KT64p != k->K64p) (void)hipFree(k->KT64p);
+  if (k->KTbf && k->KTbf != k->Kbf) (void)hipFree(k->KTbf);
+  if (k->Kbf) (void)hipFree(k->Kbf);
   if (k->K64p) (void)hipFree(k->K64p);
   if (k->KT && k->KT != k->K) (void)hipFree(k->KT);
   if (k->K) (void)hipFree(k->K);
@@ -420,7 +435,6 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   if (B == 0) return OTLM_OK;
   if (!D || !Y || !W || !logV) return OTLM_E_INVALID;
   if (B > (1 << 24)) return OTLM_E_INVALID;
-  if (p->prec != OTLM_PREC_FP32) return OTLM_E_UNSUPPORTED;
   const bool exact = p->wstep == OTLM_WSTEP_EXACT;
   const bool fp64 = p->refine == OTLM_REFINE_FP64;
   if (exact && (kdim > PN_K || prox_newton_smem((int)k->n, sizeof(double)) > 65536)) return OTLM_E_UNSUPPORTED;
@@ -504,13 +518,20 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   };
 
   // One FP32 iteration (bulk phase or FP32 refinement); `it` counts from 1 over the whole solve.
-  auto iterate32 = [&](int it, bool chk) {
+  auto iterate32 = [&](int it, bool chk, bool bf16) {
     const bool mm_step = !exact || it <= OTLM_MM_WARMUP;
     {  // s = K v, r = log(s / a)
-      ProfScope ps(k, PROF_KV32, s);
-      GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
       EpiSrc e{ws.S, mm_step ? ws.R : nullptr, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
-      gemm(bm_k, bn_k, g, e, s);
+      if (bf16) {
+        ProfScope ps(k, PROF_KVBF, s);
+        GemmArgsBf16 g{ws.Vbf, (int)np, k->Kbf, (int)np, M, (int)np, (int)np};
+        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + GB_BM - 1) / GB_BM));
+        hipLaunchKernelGGL(gemm_nt_bf16<EpiSrc>, grid, dim3(256), 0, s, g, e);
+      } else {
+        ProfScope ps(k, PROF_KV32, s);
+        GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
+        gemm(bm_k, bn_k, g, e, s);
+      }
     }
     if (!mm_step) {  // weight prox solved by active-set Newton
       ProfScope ps(k, PROF_W32, s);
@@ -526,14 +547,21 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     {  // a = D w, u = a / s
       ProfScope ps(k, PROF_U32, s);
       GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
-      EpiUscale e{ws.A, ws.U, ws.S, (int)np, (int)n, false};
+      EpiUscale e{ws.A, ws.U, ws.S, (int)np, (int)n, false, bf16 ? ws.Ubf : nullptr};
       gemm(64, 128, g, e, s);
     }
     {  // t = K^T u, v = prox(t | y) / t
-      ProfScope ps(k, PROF_KTU32, s);
-      GemmArgs g{ws.U, (int)np, k->KT, (int)np, M, (int)np, (int)np};
-      EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false};
-      gemm(bm_k, bn_k, g, e, s);
+      EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false, bf16 ? ws.Vbf : nullptr};
+      if (bf16) {
+        ProfScope ps(k, PROF_KTUBF, s);
+        GemmArgsBf16 g{ws.Ubf, (int)np, k->KTbf, (int)np, M, (int)np, (int)np};
+        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + GB_BM - 1) / GB_BM));
+        hipLaunchKernelGGL(gemm_nt_bf16<EpiProx>, grid, dim3(256), 0, s, g, e);
+      } else {
+        ProfScope ps(k, PROF_KTU32, s);
+        GemmArgs g{ws.U, (int)np, k->KT, (int)np, M, (int)np, (int)np};
+        gemm(bm_k, bn_k, g, e, s);
+      }
     }
   };
   // One FP64 iteration (refinement phase, exact weight prox).
@@ -566,13 +594,13 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
   };
   // Runs one phase; returns the last iteration index or a negative status.
-  auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, int nts_phase) -> int {
+  auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase) -> int {
     int it = it0;
     for (int j = 1; j <= cap; ++j) {
       it = it0 + j;
       const bool chk = (tol > 0.0) && (j % p->check_every == 0 || j == cap);
       if (use64) iterate64(it, chk);
-      else iterate32(it, chk);
+      else iterate32(it, chk, bf16);
       if (chk) {
         {
           ProfScope ps(k, PROF_CHECK, s);
@@ -591,7 +619,13 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   };
 
   const bool refine = p->refine != OTLM_REFINE_NONE;
-  int last = run_phase(0, p->max_iter, refine ? p->bulk_tol : p->tol, OTLM_FP32_FLOOR, false, nts);
+  const bool bulk_bf16 = p->prec == OTLM_PREC_BF16;
+  if (bulk_bf16) {
+    hipLaunchKernelGGL(convert_f32_to_bf16, dim3(1024), dim3(256), 0, s, ws.V, ws.Vbf, (size_t)B * np);
+    OTLM_HIP(hipGetLastError());
+  }
+  int last = run_phase(0, p->max_iter, refine ? p->bulk_tol : p->tol, bulk_bf16 ? OTLM_BF16_FLOOR : OTLM_FP32_FLOOR,
+                       false, bulk_bf16, nts);
   if (last < 0) return last;
   bool state64 = false;
   if (refine) {
@@ -606,10 +640,10 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.Dp, ws.Dp64, (size_t)np * kp);
       OTLM_HIP(hipGetLastError());
       const int nts64 = (int)((np + G64_BN - 1) / G64_BN);
-      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, nts64);
+      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, false, nts64);
       state64 = true;
     } else {
-      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, nts);
+      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, false, nts);
     }
     if (last < 0) return last;
   }

@@ -15,6 +15,31 @@ enum { PEN_NONE = 0, PEN_L1 = 1, PEN_L2SQ = 2, PEN_EN = 3 };
 
 constexpr float OTLM_R_CLAMP = 1.0e30f;
 
+// FP32 -> BF16 bits, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// Elementwise FP32 -> BF16 copy (start of a BF16 phase).
+__global__ void convert_f32_to_bf16(const float* __restrict__ x, unsigned short* __restrict__ y, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = f32_to_bf16(x[i]);
+}
+
+// K = exp(-C / eps) rounded to BF16, zero padded to [np, np] (transpose = 1: K^T).
+__global__ void build_kernel_bf16(const double* __restrict__ C, int n, int np, double inv_eps, int transpose,
+                                  unsigned short* __restrict__ K) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= np || i >= np) return;
+  float v = 0.f;
+  if (i < n && j < n) v = (float)exp(-(transpose ? C[(size_t)j * n + i] : C[(size_t)i * n + j]) * inv_eps);
+  K[(size_t)i * np + j] = f32_to_bf16(v);
+}
+
 // ---------------------------------------------------------------------------
 // s = K v epilogue (Algorithm 1, source update, first half).
 // Stores s and r = log(s / a) with a = D w from the previous weight step
@@ -116,16 +141,20 @@ struct EpiUscale {
   const float* S;
   int ld, n_valid;
   bool do_red;
+  unsigned short* Ubf;  // BF16 shadow of u for a BF16 product (null: none)
   __device__ __forceinline__ void elem(int m, int n, float a, float*) const {
     const size_t o = (size_t)m * ld + n;
     if (n >= n_valid) {
       A[o] = 0.f;
       U[o] = 0.f;
+      if (Ubf) Ubf[o] = 0;
       return;
     }
     a = fmaxf(a, 0.f);
     A[o] = a;
-    U[o] = a > 0.f ? a / S[o] : 0.f;
+    const float u = a > 0.f ? a / S[o] : 0.f;
+    U[o] = u;
+    if (Ubf) Ubf[o] = f32_to_bf16(u);
   }
   __device__ __forceinline__ void row_partial(int, int, const float*) const {}
 };
@@ -194,14 +223,18 @@ struct EpiProx {
   ProxConsts pc;
   int ld, ldy, n_valid;
   bool do_red;
+  unsigned short* Vbf;  // BF16 shadow of v for a BF16 product (null: none)
   __device__ __forceinline__ void elem(int m, int n, float t, float*) const {
     const size_t o = (size_t)m * ld + n;
     if (n >= n_valid) {
       V[o] = 0.f;
+      if (Vbf) Vbf[o] = 0;
       return;
     }
     if (done[m]) return;
-    V[o] = target_scaling(pc, t, Y[(size_t)m * ldy + n]);
+    const float v = target_scaling(pc, t, Y[(size_t)m * ldy + n]);
+    V[o] = v;
+    if (Vbf) Vbf[o] = f32_to_bf16(v);
   }
   __device__ __forceinline__ void row_partial(int, int, const float*) const {}
 };

@@ -26,7 +26,8 @@ EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
             "otlm_profile_read")
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
-                   "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64")
+                   "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
+                   "kv_product_bf16", "ktu_product_bf16")
 
 
 class OtlmError(RuntimeError):

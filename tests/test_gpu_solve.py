@@ -310,3 +310,43 @@ def test_fp64_refinement_full_size_sampled():
     pick = np.sort(np.random.default_rng(3).choice(wl.B, 5, replace=False))
     ref = oracle_solve(C, D32, Y32[pick], wl, max_iter=400, tol=1e-10, mode="exact")
     assert rel_err(res["W"][pick], ref["W"]).max() <= 1e-5
+
+
+# ---------------------------------------------------------------- BF16 bulk phase
+def test_bf16_products_closed_form():
+    """D = I, one iteration with BF16 kernel products: w = K 1 and
+    v = (y / K^T 1)^{lam/(lam+eps)} within the BF16 rounding of K (2^-9 per
+    entry, all terms positive, so the sums carry at most that relative error)."""
+    n, eps, lam = 96, 0.02, 0.7
+    x = synth.grid(n)
+    C = synth.sq_cost(x, x)
+    y = as_f32(np.random.default_rng(0).uniform(0.1, 1.0, (3, n)))
+    wl = synth.Workload("identity", n=n, k=n, B=3, eps=eps, fit="kl", pen="none", lam=lam, alpha=0.0)
+    _, res = gpu_solve(C, np.eye(n, dtype=np.float32), y, wl, tol=0.0, max_iter=1, prec="bf16")
+    K = np.exp(-C / eps)
+    np.testing.assert_allclose(res["W"], np.broadcast_to(K.sum(1), (3, n)), rtol=2 ** -8)
+    np.testing.assert_allclose(np.exp(res["logV"]), (y / K.sum(0)) ** (lam / (lam + eps)), rtol=2 ** -8)
+
+
+def test_bf16_bulk_then_fp64_reaches_oracle_l1():
+    wl = synth.CONFIG2
+    idx = list(range(19))
+    D32, Y32, C = setup(wl, idx)
+    ref = oracle_solve(C, D32, Y32, wl, max_iter=400, tol=1e-10, mode="exact")
+    _, res = gpu_solve(C, D32, Y32, wl, tol=1e-9, bulk_tol=1e-3, max_iter=300, check_every=5, wstep="exact",
+                       inner_max=5, prec="bf16", refine="fp64", refine_sweeps=300)
+    assert np.all(res["status"] == otlm.STATUS_CONVERGED), res["iters"]
+    assert rel_err(res["W"], ref["W"]).max() <= 1e-5
+
+
+def test_bf16_bulk_then_fp32_ridge():
+    """Ridge workload, MM steps: BF16 bulk then FP32 sweeps reach the oracle's
+    fixed point to 1e-5 (ridge keeps the weight problem well conditioned)."""
+    import dataclasses
+    wl = dataclasses.replace(synth.CONFIG2, pen="l2sq", alpha=1e-3, B=21)
+    D32, Y32, C = setup(wl, range(21))
+    ref = oracle_solve(C, D32, Y32, wl, max_iter=3000, tol=1e-12)
+    _, res = gpu_solve(C, D32, Y32, wl, tol=1e-6, bulk_tol=1e-3, max_iter=2000, check_every=10, prec="bf16",
+                       refine="fp32", refine_sweeps=2000)
+    assert np.all(res["status"] == otlm.STATUS_CONVERGED)
+    assert rel_err(res["W"], ref["W"]).max() <= 1e-5
