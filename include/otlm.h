@@ -88,8 +88,10 @@ enum {
  * from the bulk result.  Each phase freezes a spectrum once its own test
  * passes: the stopping rule of "while not converged" is
  *   sum|u o (K v) - D w| / sum(D w) <= tol_phase   and
- *   max|dw| / max|w| * rho / (1 - rho) <= tol_phase (rho = observed contraction
- *   between tests) or max|dw| / max|w| below the phase precision's resolution.
+ *   d rho / (1 - rho) <= tol_phase, with d = max|w - w'| / max|w| the weight
+ *   change since the previous test (w' = weights then) and rho = d / d_prev
+ *   its observed contraction, or d below the phase precision's resolution and
+ *   no longer shrinking.
  * tol_phase is `bulk_tol` for a bulk phase followed by refinement, `tol`
  * otherwise. */
 typedef struct {
@@ -206,6 +208,88 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
  * null kernel. */
 int otlm_profile_enable(otlm_kernel k, int32_t on);
 int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton_iters);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches: spectra of different lengths, each with its own dictionary.
+ *
+ * Every spectrum b lives on the grid of one of `nkernels` Gibbs kernels
+ * (kernel_of[b]), so n_b = that kernel's n, and has its own dictionary D_b
+ * [n_b, kdim[b]] (the paper's X for that target).  All of them run Algorithm 1
+ * together: the kernel products of the spectra that share a kernel form one
+ * GEMM, and the products of all kernels are issued as one grouped launch per
+ * step; the dictionary work (Table 2 MM step, a = D_b w, u = a / s) is one
+ * fused workgroup per spectrum.  The weight step is the MM step of Table 2,
+ * taken p->inner_max times per outer iteration at the same s = K v (every
+ * repetition majorizes the same ProxP problem, so the limit is the one of
+ * the single step; more repetitions cut the number of kernel products).
+ * FP32 state and products (OTLM_PREC_FP32, OTLM_WSTEP_MM, no refinement).
+ *
+ * Packed arrays (device, FP32, in input order b = 0..B-1, no padding):
+ *   D      D_0, D_1, ... each [n_b, kdim[b]] row-major     (sum n_b kdim[b])
+ *   Y      y_0, y_1, ...      each [n_b]                   (sum n_b)
+ *   logU, logV                 same layout as Y
+ *   W      w_0, w_1, ...      each [kdim[b]]               (sum kdim[b])
+ * ------------------------------------------------------------------------- */
+typedef struct otlm_ragged_s* otlm_ragged;
+
+typedef struct {
+  int32_t use_graph;   /* 1 (default): each interval of check_every iterations
+                          and its convergence test are captured once as a HIP
+                          graph and replayed; 0: the same launches, eager     */
+  int32_t tile;        /* -1 (default): time the four GEMM tile shapes of the
+                          grouped kernel products (128x128, 128x64, 64x128,
+                          64x64) on the plan's own shapes at create and keep
+                          the fastest; 0..3: use that shape                  */
+  int32_t reserved[2]; /* set to 0                                            */
+} otlm_ragged_opts;
+
+/* use_graph = 1, tile = -1. */
+void otlm_ragged_default_opts(otlm_ragged_opts* o);
+
+/* Plan a ragged solve.
+ *   kernels    host array [nkernels] of kernel objects (1 <= nkernels <= 8,
+ *              n <= 4096 each, eps equal to p->eps); they must outlive the
+ *              plan, which reads their K.
+ *   kernel_of  host int32 [B]: kernel index of spectrum b.
+ *   kdim       host int32 [B]: dictionary columns of spectrum b, 1..256.
+ *   B          1 .. 2^22 spectra.
+ *   p          parameters, fixed for the plan's lifetime; wstep must be
+ *              OTLM_WSTEP_MM, prec OTLM_PREC_FP32, refine OTLM_REFINE_NONE;
+ *              inner_max (1..64) is the number of MM steps per iteration.
+ *   opts       NULL for the defaults.
+ * Allocates the plan's device state (about 5 sum(np_b) + sum(n_b kdim[b])
+ * floats), runs the tile timing and the graph capture, and synchronises
+ * `stream`.  Errors: OTLM_E_INVALID, OTLM_E_UNSUPPORTED (other precision or
+ * weight-step modes, n > 4096), OTLM_E_NOMEM, OTLM_E_HIP. */
+int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32_t* kernel_of,
+                       const int32_t* kdim, int64_t B, const otlm_params* p,
+                       const otlm_ragged_opts* opts, void* stream, otlm_ragged* out);
+
+/* Solve the planned batch for the packed D and Y (layout above).  W and logV
+ * are outputs, read as the start when p->warm == 1; logU, iters and status
+ * (int32 [B], input order) may be NULL.  Copies D (transposed) and Y into the
+ * plan, so they may change between calls.  Blocks the host once at the start
+ * (input validation) and once per check interval (active count).
+ * Errors: OTLM_E_INVALID (null arrays, called on another device than the
+ * plan's, negative or non-finite D or Y, a D column summing to 0),
+ * OTLM_E_HIP. */
+int otlm_ragged_solve(otlm_ragged r, const float* D, const float* Y, float* W, float* logU,
+                      float* logV, int32_t* iters, int32_t* status, void* stream);
+
+/* Chosen tile (tile_bm x tile_bn), the timing of the four candidates in ms
+ * (tune_ms[4], 0 when a tile was forced) and sizes[4] = {sum n_b, sum kdim[b],
+ * sum n_b kdim[b], device bytes held by the plan}.  Any output may be NULL. */
+int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* tune_ms, int64_t* sizes);
+
+/* Kernel timing of ragged solves, as otlm_profile_*, with 4 classes:
+ * [0] grouped s = K v products  [1] per-spectrum weight step  [2] grouped
+ * t = K^T u products with the target prox  [3] convergence test.  While
+ * enabled the solve launches eagerly (no graph replay). */
+int otlm_ragged_profile_enable(otlm_ragged r, int32_t on);
+int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count);
+
+/* Release a plan.  NULL is a no-op.  Synchronises the device. */
+int otlm_ragged_free(otlm_ragged r);
 
 /* Static description of an otlm_status code. */
 const char* otlm_status_str(int code);

@@ -57,8 +57,10 @@ __device__ __forceinline__ float half_wave_reduce(float v) {
   return v;
 }
 
+// One BM x BN output tile at (m0, n0); `tile` is the column-tile index passed
+// to row_partial().  Shared by the plain and the grouped launches.
 template <int BM, int BN, class Epi>
-__global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
+__device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& epi, int m0, int n0, int tile) {
   constexpr int BK = GEMM_BK, LD = GEMM_LDS_LD;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
   constexpr int A_V4 = BM * (BK / 4) / 256;
@@ -70,7 +72,6 @@ __global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
 
   f32x4 ra[A_V4], rb[B_V4];
   auto gload = [&](int kt) {
@@ -178,9 +179,41 @@ __global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
           float v[2];
           v[0] = red_op<Epi::RED_IS_MAX[0]>(red_s[0][row][0], red_s[1][row][0]);
           v[1] = red_op<Epi::RED_IS_MAX[1]>(red_s[0][row][1], red_s[1][row][1]);
-          epi.row_partial(m, blockIdx.x, v);
+          epi.row_partial(m, tile, v);
         }
       }
     }
   }
+}
+
+template <int BM, int BN, class Epi>
+__global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
+  gemm_nt_f32_tile<BM, BN, Epi>(g, epi, blockIdx.y * BM, blockIdx.x * BN, blockIdx.x);
+}
+
+// Grouped launch: up to GEMM_MAX_GROUPS independent products (each with its
+// own operands, sizes and epilogue) in one grid.  Group q owns the linear
+// workgroup range [tile0[q], tile0[q+1]); inside it the column tile runs
+// fastest, so consecutive workgroups share the A rows and the round-robin
+// placement of workgroups on the chip's 8 XCDs gives each XCD a fixed subset of
+// the Bt column blocks, which then stay in that XCD's L2.  Groups are ordered
+// by the caller (largest products first) so that the long tiles start first.
+constexpr int GEMM_MAX_GROUPS = 8;
+template <class Epi>
+struct GemmGroups {
+  int ngroups;
+  int tile0[GEMM_MAX_GROUPS + 1];
+  int ntn[GEMM_MAX_GROUPS];
+  GemmArgs g[GEMM_MAX_GROUPS];
+  Epi epi[GEMM_MAX_GROUPS];
+};
+
+template <int BM, int BN, class Epi>
+__global__ __launch_bounds__(256) void gemm_nt_f32_grouped(GemmGroups<Epi> p) {
+  const int L = blockIdx.x;
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < GEMM_MAX_GROUPS; ++i) q += (i < p.ngroups && L >= p.tile0[i]) ? 1 : 0;
+  const int t = L - p.tile0[q], tm = t / p.ntn[q], tn = t - tm * p.ntn[q];
+  gemm_nt_f32_tile<BM, BN, Epi>(p.g[q], p.epi[q], tm * BM, tn * BN, tn);
 }

@@ -25,6 +25,7 @@
 #include "gemm_nt_bf16.hpp"
 #include "objective_kernels.hpp"
 #include "prox_newton.hpp"
+#include "ragged_kernels.hpp"
 #include "solver_kernels.hpp"
 #include "solver_kernels64.hpp"
 
@@ -47,6 +48,7 @@ struct Workspace {
   float *Dp = nullptr, *DTp = nullptr;
   float4* colc = nullptr;
   float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr;
+  float* Wsnap = nullptr;  // weights at the previous convergence test
   int *done = nullptr, *iters = nullptr, *status = nullptr, *flags = nullptr;
   float* ew_prev = nullptr;
   float* ew_best = nullptr;
@@ -56,6 +58,7 @@ struct Workspace {
   // FP64 refinement state
   int64_t B64 = 0;
   double *V64 = nullptr, *S64 = nullptr, *A64 = nullptr, *U64 = nullptr, *W64 = nullptr, *Dp64 = nullptr;
+  double* Wsnap64 = nullptr;
   std::vector<void*> allocs64;
   double *os = nullptr, *ot = nullptr, *oq = nullptr;
   int64_t obj_B = 0;
@@ -68,7 +71,7 @@ struct Workspace {
     if (host_flags) (void)hipHostFree(host_flags);
     host_flags = nullptr;
     B = np = kp = 0;
-    V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = nullptr;
+    V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = Wsnap = nullptr;
     colc = nullptr;
     done = iters = status = flags = nullptr;
     ew_prev = nullptr;
@@ -81,7 +84,7 @@ struct Workspace {
     for (void* p : allocs64) (void)hipFree(p);
     allocs64.clear();
     B64 = 0;
-    V64 = S64 = A64 = U64 = W64 = Dp64 = nullptr;
+    V64 = S64 = A64 = U64 = W64 = Dp64 = Wsnap64 = nullptr;
   }
   void release_obj() {
     if (os) (void)hipFree(os);
@@ -165,8 +168,9 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.colc, (size_t)kp);
   rc |= dev_alloc(ws, &ws.psn, (size_t)B * MAX_TILES);
   rc |= dev_alloc(ws, &ws.psd, (size_t)B * MAX_TILES);
-  rc |= dev_alloc(ws, &ws.pwn, (size_t)B * MAX_TILES);
-  rc |= dev_alloc(ws, &ws.pwd, (size_t)B * MAX_TILES);
+  rc |= dev_alloc(ws, &ws.pwn, (size_t)B);
+  rc |= dev_alloc(ws, &ws.pwd, (size_t)B);
+  rc |= dev_alloc(ws, &ws.Wsnap, bk);
   rc |= dev_alloc(ws, &ws.done, (size_t)B);
   rc |= dev_alloc(ws, &ws.iters, (size_t)B);
   rc |= dev_alloc(ws, &ws.status, (size_t)B);
@@ -455,7 +459,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       return true;
     };
     if (!al(&ws.V64, bn) || !al(&ws.S64, bn) || !al(&ws.A64, bn) || !al(&ws.U64, bn) ||
-        !al(&ws.W64, (size_t)B * kp) || !al(&ws.Dp64, (size_t)np * kp)) {
+        !al(&ws.W64, (size_t)B * kp) || !al(&ws.Dp64, (size_t)np * kp) || !al(&ws.Wsnap64, (size_t)B * kp)) {
       ws.release64();
       return OTLM_E_NOMEM;
     }
@@ -483,7 +487,6 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   const int bm_k = B >= 4096 ? 128 : 64, bn_k = 128;
   const int nts = (int)((np + bn_k - 1) / bn_k);
   const int bn_w = kp >= 128 ? 128 : 64;
-  const int ntw = exact ? 1 : (int)((kp + bn_w - 1) / bn_w);
   ProxConsts pc;
   pc.fit = p->fit;
   pc.kappa = (float)(p->lambda / (p->lambda + p->eps));
@@ -501,7 +504,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
 
   auto prox_args32 = [&]() {
     ProxNewtonArgs<float, float> a;
-    a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
     a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
@@ -510,7 +513,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   };
   auto prox_args64 = [&]() {
     ProxNewtonArgs<double, double> a;
-    a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done; a.pwn = ws.pwn; a.pwd = ws.pwd;
+    a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit;
@@ -541,7 +544,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     } else {  // MM weight step
       ProfScope ps(k, PROF_W32, s);
       GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
-      EpiWupd e{ws.W, ws.colc, ws.done, ws.pwn, ws.pwd, (int)kp, (int)kdim, p->pen, ntw, chk};
+      EpiWupd e{ws.W, ws.colc, ws.done, (int)kp, (int)kdim, p->pen, false};
       gemm(64, bn_w, g, e, s);
     }
     {  // a = D w, u = a / s
@@ -594,8 +597,21 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
   };
   // Runs one phase; returns the last iteration index or a negative status.
+  // Weight change since the previous test (init: snapshot at the phase start).
+  auto weight_change = [&](bool use64, int init) {
+    const dim3 grid((unsigned)((B + 3) / 4));
+    if (use64) {
+      auto kern = interval_change<double>;
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W64, (int)kp, (int)kdim, M, ws.Wsnap64, init, ws.pwn,
+                         ws.pwd);
+    } else {
+      auto kern = interval_change<float>;
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W, (int)kp, (int)kdim, M, ws.Wsnap, init, ws.pwn, ws.pwd);
+    }
+  };
   auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase) -> int {
     int it = it0;
+    if (tol > 0.0) weight_change(use64, 1);
     for (int j = 1; j <= cap; ++j) {
       it = it0 + j;
       const bool chk = (tol > 0.0) && (j % p->check_every == 0 || j == cap);
@@ -604,9 +620,10 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       if (chk) {
         {
           ProfScope ps(k, PROF_CHECK, s);
+          weight_change(use64, 0);
           hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts_phase, ws.pwn, ws.pwd,
-                             ntw, M, (float)tol, floor_w, p->check_every, it, ws.ew_prev, ws.ew_best, ws.stall,
-                             ws.done, ws.iters, ws.status, ws.flags);
+                             M, (float)tol, floor_w, it, ws.ew_prev, ws.ew_best, ws.stall, ws.done, ws.iters,
+                             ws.status, ws.flags, nullptr);
         }
         if (hipGetLastError() != hipSuccess) return OTLM_E_HIP;
         if (hipMemcpyAsync(ws.host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -693,3 +710,5 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
 }
 
 }  // extern "C"
+
+#include "ragged.hpp"

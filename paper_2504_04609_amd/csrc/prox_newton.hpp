@@ -41,8 +41,6 @@ struct ProxNewtonArgs {
   const float* DTp;    // [kp, ld_dt] its transpose (coalesced column sweeps)
   const float4* colc;  // per column {1/x_j, ...}
   const int* done;
-  float* pwn;          // e_w partials, one tile per spectrum
-  float* pwd;
   int* nit;            // Newton iterations done, accumulated per spectrum
   int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
@@ -400,26 +398,10 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     __syncthreads();
   }
 
-  // ---- write back and the weight-change reductions for the convergence test
-  double dw = 0.0, wm = 0.0;
-  if (tid < k) {
-    const TW wold = wrow[tid];
-    const TW wnew = (TW)w[tid];
-    wrow[tid] = wnew;
-    dw = fabs((double)wnew - (double)wold);
-    wm = fabs((double)wnew);
-  }
+  // ---- write back
+  if (tid < k) wrow[tid] = (TW)w[tid];
   if (tid < PN_K && tid >= k && tid < p.ld_w) wrow[tid] = (TW)0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    dw = fmax(dw, __shfl_xor(dw, off, 64));
-    wm = fmax(wm, __shfl_xor(wm, off, 64));
-  }
-  if (tid == 0) {
-    p.pwn[b] = (float)dw;
-    p.pwd[b] = (float)wm;
-    p.nit[b] += it;
-  }
+  if (tid == 0) p.nit[b] += it;
 }
 
 inline size_t prox_newton_smem(int n, size_t s_bytes) {

@@ -92,18 +92,16 @@ struct EpiSrc {
 //   squared l2:  w_j = omega(nu_j + log g_j) / g_j,              g_j = alpha / (eps x_j)
 //   elastic net: w_j = omega(nu_j - alpha/(eps x_j) + log g_j) / g_j,  g_j = beta / (eps x_j)
 // colc holds per column [1/x_j, shift_j, g_j, log g_j].  Frozen spectra keep
-// their weights.  Reductions: max_j |w_j - w'_j| and max_j |w_j|.
+// their weights.
 struct EpiWupd {
-  static constexpr int NRED = 2;
-  static constexpr bool RED_IS_MAX[2] = {true, true};
+  static constexpr int NRED = 0;
+  static constexpr bool RED_IS_MAX[2] = {false, false};
   float* W;
   const float4* colc;
   const int* done;
-  float* part_num;
-  float* part_den;
-  int ld, k_valid, pen, ntiles;
+  int ld, k_valid, pen;
   bool do_red;
-  __device__ __forceinline__ void elem(int m, int j, float c, float* red) const {
+  __device__ __forceinline__ void elem(int m, int j, float c, float*) const {
     const size_t o = (size_t)m * ld + j;
     if (j >= k_valid) {
       W[o] = 0.f;
@@ -120,15 +118,9 @@ struct EpiWupd {
     } else {  // PEN_L2SQ (shift 0) and PEN_EN share the Lambert-W form
       w = wright_omega<float>(nu - cc.y + cc.w) / cc.z;
     }
-    if (done[m]) w = wold;
-    else W[o] = w;
-    red[0] = fmaxf(red[0], fabsf(w - wold));
-    red[1] = fmaxf(red[1], fabsf(w));
+    if (!done[m]) W[o] = w;
   }
-  __device__ __forceinline__ void row_partial(int m, int tile, const float* v) const {
-    part_num[(size_t)m * ntiles + tile] = v[0];
-    part_den[(size_t)m * ntiles + tile] = v[1];
-  }
+  __device__ __forceinline__ void row_partial(int, int, const float*) const {}
 };
 
 // ---------------------------------------------------------------------------
@@ -332,47 +324,81 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
   }
 }
 
+// Weight change over a check interval, per spectrum: max_j |w_j - w^snap_j|
+// and max_j |w_j|, where w^snap holds the weights at the previous test; then
+// w^snap = w.  With init = 1 it only takes the snapshot (start of a phase).
+// NaN propagates into the maxima.  One wave per spectrum.
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
+template <class T>
+__global__ __launch_bounds__(256) void interval_change(const T* __restrict__ W, int ld, int k, int B,
+                                                       T* __restrict__ snap, int init, float* __restrict__ pwn,
+                                                       float* __restrict__ pwd) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= B) return;
+  double dw = 0.0, wm = 0.0;
+  for (int j = lane; j < k; j += 64) {
+    const size_t o = (size_t)b * ld + j;
+    const T w = W[o];
+    dw = nan_max(dw, fabs((double)w - (double)snap[o]));
+    wm = nan_max(wm, fabs((double)w));
+    snap[o] = w;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    dw = nan_max(dw, __shfl_xor(dw, off, 64));
+    wm = nan_max(wm, __shfl_xor(wm, off, 64));
+  }
+  if (lane == 0 && !init) {
+    pwn[b] = (float)dw;
+    pwd[b] = (float)wm;
+  }
+}
+
 // Convergence test for every spectrum (the stopping rule of "while not
-// converged"): e_src = sum|u s - a| / sum a and e_w = max|dw| / max|w|, both
-// assembled from the per-tile partials in a fixed order.  The weight test uses
-// the a-posteriori bound of a linearly converging iteration: with the observed
-// contraction rho = (e_w / e_w_prev)^(1/c) over the c iterations since the last
-// test, the distance to the limit is about e_w rho / (1 - rho).  A spectrum
-// stops when e_src <= tol and either that bound is <= tol or e_w has reached
-// the resolution `floor` of the phase's precision (the iteration cannot move w
-// any further).  A spectrum whose e_w has not improved on its best value for
-// OTLM_STALL_CHECKS tests has reached the noise floor of its precision on an
-// ill-conditioned problem: it stops with status 8.  One workgroup; also counts
-// the spectra still active into *active.
+// converged").  e_src = sum|u s - a| / sum a, assembled from the per-tile
+// partials in a fixed order, and d = max|w - w^snap| / max|w|, the relative
+// weight change over the check interval.  For a linearly converging iteration
+// the interval changes shrink geometrically, rho = d / d_prev, and the
+// distance to the limit is d rho / (1 - rho) (the a-posteriori bound of the
+// c-step map; exact for a geometric sequence).  A spectrum stops when
+// e_src <= tol and either that bound is <= tol, or d has reached the resolution
+// `floor` of the phase's precision without shrinking since the last test (the
+// iteration no longer moves w beyond its rounding noise; a change below the
+// floor that still shrinks is real, slow contraction and the bound decides).
+// A spectrum whose d has not improved on its best value for OTLM_STALL_CHECKS
+// tests has reached the noise floor of its precision on an ill-conditioned
+// problem: it stops with status 8.  One workgroup; also counts the spectra
+// still active into *active.  The iteration index recorded for a stopping
+// spectrum is `it`, or *it_dev when it_dev is not null.
 constexpr int OTLM_STALL_CHECKS = 6;
 __global__ void check_convergence(const float* __restrict__ psn, const float* __restrict__ psd, int nts,
-                                  const float* __restrict__ pwn, const float* __restrict__ pwd, int ntw, int B,
-                                  float tol, float floor_w, int c, int it, float* __restrict__ ew_prev,
-                                  float* __restrict__ ew_best, int* __restrict__ stall,
-                                  int* __restrict__ done, int* __restrict__ iters, int* __restrict__ status,
-                                  int* __restrict__ active) {
+                                  const float* __restrict__ pwn, const float* __restrict__ pwd, int B, float tol,
+                                  float floor_w, int it, float* __restrict__ ew_prev, float* __restrict__ ew_best,
+                                  int* __restrict__ stall, int* __restrict__ done, int* __restrict__ iters,
+                                  int* __restrict__ status, int* __restrict__ active,
+                                  const int* __restrict__ it_dev) {
   __shared__ int cnt[1024];
+  if (it_dev) it = it_dev[0];  // iteration index kept on the device (captured chunks)
   int count = 0;
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     if (!done[b]) {
-      float num = 0.f, den = 0.f, dw = 0.f, wm = 0.f;
+      float num = 0.f, den = 0.f;
       for (int t = 0; t < nts; ++t) {
         num += psn[(size_t)b * nts + t];
         den += psd[(size_t)b * nts + t];
       }
-      for (int t = 0; t < ntw; ++t) {
-        dw = fmaxf(dw, pwn[(size_t)b * ntw + t]);
-        wm = fmaxf(wm, pwd[(size_t)b * ntw + t]);
-      }
+      const float dw = pwn[b], wm = pwd[b];
       const float esrc = den > 0.f ? num / den : 0.f;
       const float ew = wm > 0.f ? dw / wm : 0.f;
       const float prev = ew_prev[b];
       ew_prev[b] = ew;
       float bound = INFINITY;
+      const bool shrinking = prev > 0.f && ew < prev;
       if (ew == 0.f) {
         bound = 0.f;
-      } else if (prev > 0.f && ew < prev) {
-        const float rho = powf(ew / prev, 1.f / (float)c);
+      } else if (shrinking) {
+        const float rho = ew / prev;
         bound = ew * rho / (1.f - rho);
       }
       int st = 0;
@@ -383,7 +409,7 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
         stall[b] += 1;
       }
       if (!isfinite(num + den + dw + wm)) st = 4;
-      else if (esrc <= tol && (bound <= tol || ew <= floor_w)) st = 1;
+      else if (esrc <= tol && (bound <= tol || (ew <= floor_w && !shrinking))) st = 1;
       else if (stall[b] >= OTLM_STALL_CHECKS) st = 8;
       if (st) {
         done[b] = 1;

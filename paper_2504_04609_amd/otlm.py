@@ -24,10 +24,13 @@ STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED = 1, 2, 4,
 
 EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info",
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
-            "otlm_profile_read")
+            "otlm_profile_read", "otlm_ragged_default_opts", "otlm_ragged_create", "otlm_ragged_solve",
+            "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read", "otlm_ragged_free")
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
                    "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
                    "kv_product_bf16", "ktu_product_bf16")
+RAGGED_PROFILE_CLASSES = ("kv_product", "weight_step", "ktu_product", "convergence_test")
+RAGGED_TILES = ((128, 128), (128, 64), (64, 128), (64, 64))
 
 
 class OtlmError(RuntimeError):
@@ -42,6 +45,10 @@ class Params(ctypes.Structure):
                 ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32), ("wstep", ctypes.c_int32),
                 ("inner_max", ctypes.c_int32)]
+
+
+class RaggedOpts(ctypes.Structure):
+    _fields_ = [("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -67,8 +74,20 @@ def load() -> ctypes.CDLL:
     lib.otlm_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.otlm_status_str.argtypes = [ctypes.c_int]
     lib.otlm_status_str.restype = ctypes.c_char_p
+    lib.otlm_ragged_default_opts.argtypes = [ctypes.POINTER(RaggedOpts)]
+    lib.otlm_ragged_default_opts.restype = None
+    lib.otlm_ragged_create.argtypes = [vp, ctypes.c_int32, vp, vp, i64, ctypes.POINTER(Params),
+                                       ctypes.POINTER(RaggedOpts), vp, ctypes.POINTER(vp)]
+    lib.otlm_ragged_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.otlm_ragged_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    lib.otlm_ragged_profile_enable.argtypes = [vp, ctypes.c_int32]
+    lib.otlm_ragged_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    lib.otlm_ragged_free.argtypes = [vp]
     for name in ("otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info", "otlm_solve_batch", "otlm_objective",
-                 "otlm_profile_enable", "otlm_profile_read"):
+                 "otlm_profile_enable", "otlm_profile_read", "otlm_ragged_create", "otlm_ragged_solve",
+                 "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read",
+                 "otlm_ragged_free"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -216,3 +235,94 @@ class GibbsKernel:
         _check(load().otlm_objective(self.handle, _ptr(C), _ptr(D), k, _ptr(Y), B, ctypes.byref(p), _ptr(W),
                                      _ptr(logU), _ptr(logV), _ptr(out), _stream(stream)), "otlm_objective")
         return out
+
+
+class RaggedPlan:
+    """A planned ragged batch (otlm_ragged_create): spectrum b uses kernel
+    kernels[kernel_of[b]] (so n_b = that kernel's n) and a dictionary with
+    kdim[b] columns.  Packed layouts as in include/otlm.h."""
+
+    def __init__(self, kernels, kernel_of, kdim, params: SolveParams, use_graph: bool = True, tile: int = -1,
+                 stream=None):
+        import numpy as np
+        self.kernels = list(kernels)  # the plan reads their K: keep them alive
+        self.kernel_of = np.ascontiguousarray(kernel_of, dtype=np.int32)
+        self.kdim = np.ascontiguousarray(kdim, dtype=np.int32)
+        if self.kernel_of.shape != self.kdim.shape or self.kernel_of.ndim != 1:
+            raise OtlmError("kernel_of and kdim must be 1-D arrays of one length")
+        self.B = int(self.kernel_of.size)
+        if self.B and (self.kernel_of.min() < 0 or self.kernel_of.max() >= len(self.kernels)):
+            raise OtlmError("kernel_of out of range")
+        ns = np.array([kk.n for kk in self.kernels], dtype=np.int64)
+        self.n = ns[self.kernel_of] if self.B else np.zeros(0, np.int64)
+        self.y_off = np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64)
+        self.w_off = np.concatenate([[0], np.cumsum(self.kdim)]).astype(np.int64)
+        self.d_off = np.concatenate([[0], np.cumsum(self.n * self.kdim)]).astype(np.int64)
+        self.params = params
+        lib = load()
+        handles = (ctypes.c_void_p * len(self.kernels))(*[kk.handle for kk in self.kernels])
+        o = RaggedOpts()
+        lib.otlm_ragged_default_opts(ctypes.byref(o))
+        o.use_graph, o.tile = int(use_graph), int(tile)
+        p = params.c()
+        h = ctypes.c_void_p()
+        _check(lib.otlm_ragged_create(handles, len(self.kernels), self.kernel_of.ctypes.data_as(ctypes.c_void_p),
+                                      self.kdim.ctypes.data_as(ctypes.c_void_p), self.B, ctypes.byref(p),
+                                      ctypes.byref(o), _stream(stream), ctypes.byref(h)), "otlm_ragged_create")
+        self.handle = h
+
+    def info(self):
+        bm, bn = ctypes.c_int32(), ctypes.c_int32()
+        tune = (ctypes.c_double * 4)()
+        sizes = (ctypes.c_int64 * 4)()
+        _check(load().otlm_ragged_info(self.handle, ctypes.byref(bm), ctypes.byref(bn), tune, sizes),
+               "otlm_ragged_info")
+        return {"tile": (bm.value, bn.value), "tune_ms": list(tune), "bins": sizes[0], "columns": sizes[1],
+                "dict_entries": sizes[2], "device_bytes": sizes[3]}
+
+    def profile(self, on: bool = True):
+        _check(load().otlm_ragged_profile_enable(self.handle, int(on)), "otlm_ragged_profile_enable")
+
+    def profile_read(self):
+        ms = (ctypes.c_double * len(RAGGED_PROFILE_CLASSES))()
+        cnt = (ctypes.c_int64 * len(RAGGED_PROFILE_CLASSES))()
+        _check(load().otlm_ragged_profile_read(self.handle, ms, cnt), "otlm_ragged_profile_read")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(RAGGED_PROFILE_CLASSES)}
+
+    def solve(self, D, Y, W=None, logV=None, want_logU=True, stream=None):
+        """otlm_ragged_solve on packed CUDA tensors D [sum n_b k_b], Y [sum n_b].
+        Returns packed W [sum k_b], logU / logV [sum n_b], iters / status [B]."""
+        import torch
+        nb, kb, db = int(self.y_off[-1]), int(self.w_off[-1]), int(self.d_off[-1])
+        _need(D, torch.float32, (db,), "D")
+        _need(Y, torch.float32, (nb,), "Y")
+        dev = Y.device
+        if self.params.warm:
+            _need(W, torch.float32, (kb,), "W")
+            _need(logV, torch.float32, (nb,), "logV")
+        else:
+            W = torch.empty(kb, device=dev, dtype=torch.float32) if W is None else W
+            logV = torch.empty(nb, device=dev, dtype=torch.float32) if logV is None else logV
+        logU = torch.empty(nb, device=dev, dtype=torch.float32) if want_logU else None
+        iters = torch.empty(self.B, device=dev, dtype=torch.int32)
+        status = torch.empty(self.B, device=dev, dtype=torch.int32)
+        _check(load().otlm_ragged_solve(self.handle, _ptr(D), _ptr(Y), _ptr(W), _ptr(logU), _ptr(logV), _ptr(iters),
+                                        _ptr(status), _stream(stream)), "otlm_ragged_solve")
+        return {"W": W, "logU": logU, "logV": logV, "iters": iters, "status": status}
+
+    def unpack_w(self, W, b):
+        return W[int(self.w_off[b]):int(self.w_off[b + 1])]
+
+    def unpack_n(self, X, b):
+        return X[int(self.y_off[b]):int(self.y_off[b + 1])]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().otlm_ragged_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

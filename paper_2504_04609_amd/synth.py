@@ -129,3 +129,77 @@ CONFIG5_EVAL = dataclasses.replace(CONFIG2, name="heldout_n1024_k64_l1_eps2e-3",
                                    seed=6, dict_seed=2)
 CONFIG5_TRAIN = dataclasses.replace(CONFIG5_EVAL, name="train_n1024_k64_l1_eps2e-3", B=200_000,
                                     seed=5)
+
+
+# ---------------------------------------------------------------- ragged batch
+RAGGED_NS = (256, 512, 1024, 2048)
+RAGGED_KS = (16, 32, 64, 128)
+
+
+@dataclasses.dataclass
+class RaggedWorkload:
+    """Spectra of uneven length, each with its own grid and dictionary.
+
+    Spectrum b draws n_b from RAGGED_NS and k_b from RAGGED_KS, then its own
+    dictionary (centres U[0.1, 0.9], sigmas U[0.01, 0.05], truncated at 5 sigma,
+    unit mass) and a target built as for the single-target workload (one shift
+    U[-shift, shift], gain 1, |N(0, 1e-3)| noise), all from PCG64(SeedSequence([seed, b])).
+    """
+    name: str = "ragged_8192_l2tv_ridge"
+    B: int = 8192
+    eps: float = 0.005
+    fit: str = "l2tv"
+    pen: str = "l2sq"
+    lam: float = 1.0
+    lam2: float = 0.1
+    alpha: float = 1e-3
+    beta: float = 0.0
+    seed: int = 4
+    shift: float = 0.02
+    ns: tuple = RAGGED_NS
+    ks: tuple = RAGGED_KS
+
+    def spectrum(self, b: int):
+        """(n, k, D [n, k] FP64, y [n] FP64) of spectrum b."""
+        rng = rng_for(self.seed, b)
+        n = int(rng.choice(self.ns))
+        k = int(rng.choice(self.ks))
+        x = grid(n)
+        c = rng.uniform(0.1, 0.9, k)
+        s = rng.uniform(0.01, 0.05, k)
+        D = gaussian_peaks(x, c, s)
+        w_true = rng.exponential(1.0, k)
+        delta = rng.uniform(-self.shift, self.shift)
+        eta = np.abs(rng.normal(0.0, 1e-3, n))
+        y = gaussian_peaks(x, c + delta, s) @ w_true + eta
+        return n, k, D, y
+
+    def sizes(self, idx=None):
+        """(n_b, k_b) for the spectra in idx, without building dictionaries."""
+        idx = range(self.B) if idx is None else idx
+        out = []
+        for b in idx:
+            rng = rng_for(self.seed, int(b))
+            out.append((int(rng.choice(self.ns)), int(rng.choice(self.ks))))
+        return out
+
+    def cost(self, n: int) -> np.ndarray:
+        """Squared-distance cost on the n-bin grid."""
+        x = grid(n)
+        return sq_cost(x, x)
+
+    def pack(self, idx=None):
+        """Packed FP32 inputs of the spectra in idx (input order): kernel index
+        of each spectrum into the sorted list of distinct n, the list itself,
+        k per spectrum, D_0 D_1 ... (each [n_b, k_b] row-major) and y_0 y_1 ..."""
+        idx = list(range(self.B)) if idx is None else [int(b) for b in idx]
+        specs = [self.spectrum(b) for b in idx]
+        ns = sorted({sp[0] for sp in specs})
+        kernel_of = np.array([ns.index(sp[0]) for sp in specs], dtype=np.int32)
+        kdim = np.array([sp[1] for sp in specs], dtype=np.int32)
+        D = np.concatenate([sp[2].astype(np.float32).ravel() for sp in specs])
+        Y = np.concatenate([sp[3].astype(np.float32) for sp in specs])
+        return kernel_of, ns, kdim, D, Y
+
+
+CONFIG4 = RaggedWorkload()

@@ -60,3 +60,27 @@ def test_argument_errors_before_any_launch():
     assert lib.otlm_free_kernel(None) == 0
     assert lib.otlm_status_str(-1) == b"invalid argument"
     assert lib.otlm_status_str(0) == b"ok"
+
+
+@needs_lib
+def test_ragged_opts_and_argument_errors():
+    lib = otlm.load()
+    assert ctypes.sizeof(otlm.RaggedOpts) == 16
+    o = otlm.RaggedOpts()
+    lib.otlm_ragged_default_opts(ctypes.byref(o))
+    assert o.use_graph == 1 and o.tile == -1
+    p = otlm.Params()
+    lib.otlm_default_params(ctypes.byref(p))
+    h = ctypes.c_void_p()
+    ko = (ctypes.c_int32 * 2)(0, 0)
+    kd = (ctypes.c_int32 * 2)(4, 4)
+    # no kernels / bad counts / null output: rejected before any HIP call
+    assert lib.otlm_ragged_create(None, 1, ko, kd, 2, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    kernels = (ctypes.c_void_p * 1)(None)
+    assert lib.otlm_ragged_create(kernels, 0, ko, kd, 2, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert lib.otlm_ragged_create(kernels, 1, ko, kd, 0, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert lib.otlm_ragged_create(kernels, 1, ko, kd, 2, ctypes.byref(p), None, None, None) == -1
+    assert lib.otlm_ragged_create(kernels, 9, ko, kd, 2, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert lib.otlm_ragged_solve(None, None, None, None, None, None, None, None, None) == -1
+    assert lib.otlm_ragged_info(None, None, None, None, None) == -1
+    assert lib.otlm_ragged_free(None) == 0
