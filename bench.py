@@ -19,6 +19,13 @@ Arms (all cold start, all through the C-ABI):
   exact_fp32_64  the same with an FP64 refinement phase (headline)
   exact_bf16_64  BF16 kernel products in the bulk phase, then the FP64 refinement
 
+Secondary row "ragged" (skip with --no-ragged): 8192 spectra with their own
+grid length n in {256, 512, 1024, 2048} and dictionary (k in {16..128}
+Gaussian peaks), L2 + TV datafit (1.0, 0.1), ridge 1e-3, eps 0.005, FP32,
+solved by one otlm_ragged plan (grouped kernel products, banded dictionary
+steps with 4 MM steps per iteration, graph-replayed check intervals), checked
+against the oracle on one spectrum per (n, k) cell.
+
 Prints one JSON line; the roofline entry is the kernel class with the largest
 total time in the headline arm, timed with HIP events on the solve's stream
 inside the timed region.
@@ -88,6 +95,87 @@ def roofline(prof, B, n, k, phi):
     return entry
 
 
+def ragged_row(args, otlm, synth, torch):
+    """Ragged batch: time per solve, spectra/s, sampled oracle check, roofline."""
+    wl = synth.CONFIG4
+    kernel_of, ns, kdim, D, Y = wl.pack()
+    dev = "cuda:0"
+    kernels = [otlm.GibbsKernel(torch.as_tensor(wl.cost(n), device=dev), wl.eps) for n in ns]
+    Dt, Yt = torch.as_tensor(D, device=dev), torch.as_tensor(Y, device=dev)
+    params = otlm.SolveParams(eps=wl.eps, fit=wl.fit, pen=wl.pen, lam=wl.lam, lam2=wl.lam2, alpha=wl.alpha,
+                              tol=1e-6, max_iter=3000, check_every=10, inner_max=4)
+    plan = otlm.RaggedPlan(kernels, kernel_of, kdim, params)
+    for _ in range(args.warmup):
+        plan.solve(Dt, Yt)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, min(args.steps, 3))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.solve(Dt, Yt)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = 1e3 * statistics.median(times)
+    W = out["W"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    # kernel classes and algorithmic work from one eager, event-timed solve
+    plan.profile(True)
+    plan.solve(Dt, Yt)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    info = plan.info()
+    (kv_ms, kv_n), (ws_ms, ws_n), (kt_ms, kt_n) = prof["kv_product"], prof["weight_step"], prof["ktu_product"]
+    prod_ms = (kv_ms * kv_n + kt_ms * kt_n) / max(kv_n + kt_n, 1)
+    prod = {"kernel": "grouped kernel products (s = K v, t = K^T u)", "bound": "mfma", "unit": "TFLOP/s",
+            "peak": PEAK["fp32_mfma"], "ms_per_launch": prod_ms, "launches": kv_n + kt_n, "traffic": None,
+            "flops_per_launch": 2.0 * prof["product_macs"] / max(kv_n + kt_n, 1)}
+    prod["achieved"] = prod["flops_per_launch"] / (prod_ms * 1e-3) / 1e12
+    wstep = {"kernel": "per-spectrum weight step", "bound": "hbm", "unit": "GB/s", "peak": 8000.0,
+             "ms_per_launch": ws_ms, "launches": ws_n, "traffic": None,
+             "bytes_per_launch": prof["weight_step_bytes"] / max(ws_n, 1)}
+    wstep["achieved"] = wstep["bytes_per_launch"] / (ws_ms * 1e-3) / 1e9
+    for e in (prod, wstep):
+        e["frac"] = e["achieved"] / e["peak"]
+    dominant = prod if prod_ms * (kv_n + kt_n) >= ws_ms * ws_n else wstep
+    row = {"workload": wl.name, "B": wl.B, "n": list(ns), "k": sorted(set(int(x) for x in kdim)),
+           "datafit": "l2+tv", "lambda": wl.lam, "lambda2": wl.lam2, "penalty": "l2sq", "alpha": wl.alpha,
+           "eps": wl.eps, "dtype": "f32", "inner_mm_steps": 4, "tile": info["tile"], "tile_tune_ms": info["tune_ms"],
+           "ms_per_solve": ms, "ms_all": [1e3 * t for t in times], "spectra_per_s": wl.B / (ms * 1e-3),
+           "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+           "iters_quantiles_50_90_99": [float(x) for x in np.quantile(iters, [0.5, 0.9, 0.99])],
+           "status_counts": {int(a): int(b) for a, b in zip(*np.unique(status, return_counts=True))},
+           "kernels_ms_per_launch": {c: v[0] for c, v in prof.items() if isinstance(v, tuple)},
+           "kernel_launches": {c: v[1] for c, v in prof.items() if isinstance(v, tuple)},
+           "roofline": dominant, "roofline_other": wstep if dominant is prod else prod}
+    if not args.no_cpu:
+        import oracle as orc
+        n_of = np.array(ns)[kernel_of]
+        w_off = np.concatenate([[0], np.cumsum(kdim)])
+        d_off = np.concatenate([[0], np.cumsum(n_of * kdim)])
+        y_off = np.concatenate([[0], np.cumsum(n_of)])
+        pick = {}
+        for b in range(wl.B):
+            pick.setdefault((int(n_of[b]), int(kdim[b])), b)
+        errs = []
+        for (n, k), b in sorted(pick.items()):
+            K = orc.gibbs_kernel(wl.cost(n), wl.eps)
+            Db = D[d_off[b]:d_off[b + 1]].reshape(n, k).astype(np.float64)
+            yb = Y[y_off[b]:y_off[b + 1]].astype(np.float64)
+            ref = orc.solve(K, Db, yb[None], fit=wl.fit, pen=wl.pen, eps=wl.eps, lam=wl.lam, lam2=wl.lam2,
+                            alpha=wl.alpha, max_iter=2000, tol=1e-12, mode="exact")["W"][0]
+            w = W[w_off[b]:w_off[b + 1]].astype(np.float64)
+            errs.append(float(np.linalg.norm(w - ref) / np.linalg.norm(ref)))
+        row["check"] = {"spectra": len(errs), "sample": "first spectrum of every (n, k) cell",
+                        "max_err": max(errs), "median_err": float(np.median(errs)),
+                        "fraction_le_1e-5": float(np.mean(np.array(errs) <= 1e-5))}
+    plan.close()
+    print(f"# ragged: {ms:.1f} ms/solve, mean iters {row['iters_mean']:.1f}, max {row['iters_max']}",
+          file=sys.stderr, flush=True)
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +184,8 @@ def main():
     ap.add_argument("--sample", type=int, default=8)
     ap.add_argument("--arms", default="paper_mm,exact_fp32,exact_bf16_64,exact_fp32_64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch row")
+    ap.add_argument("--ragged-only", action="store_true", help="run only the ragged-batch row")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here (the spectra are "
@@ -119,6 +209,8 @@ def main():
     arms = [a for a in args.arms.split(",") if a]
     headline = "exact_fp32_64" if "exact_fp32_64" in arms else arms[-1]
 
+    if args.ragged_only:
+        arms = []
     results = {}
     for arm in arms:
         params = arm_params(arm, wl, otlm)
@@ -168,6 +260,11 @@ def main():
             solved[arm] = {"fraction": float(np.mean(err <= 1e-5)), "max_err": float(err.max()),
                            "median_err": float(np.median(err))}
 
+    ragged = None if args.no_ragged else ragged_row(args, otlm, synth, torch)
+    if args.ragged_only:
+        print(json.dumps({"ragged": ragged}), flush=True)
+        return
+
     def value_of(arm):
         frac = solved[arm]["fraction"] if solved[arm] is not None else float("nan")
         return B * frac / (results[arm]["ms_median"] * 1e-3)
@@ -199,6 +296,8 @@ def main():
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu
+    if ragged is not None:
+        line["ragged"] = ragged
     print(json.dumps(line), flush=True)
 
 

@@ -284,9 +284,14 @@ int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* 
 /* Kernel timing of ragged solves, as otlm_profile_*, with 4 classes:
  * [0] grouped s = K v products  [1] per-spectrum weight step  [2] grouped
  * t = K^T u products with the target prox  [3] convergence test.  While
- * enabled the solve launches eagerly (no graph replay). */
+ * enabled the solve launches eagerly (no graph replay) and counts the
+ * algorithmic work of the timed launches into work[2] (may be NULL):
+ * [0] multiply-adds of the kernel products, sum over launches and active
+ * spectra of n_b^2 (both products); [1] bytes of the weight steps, per active
+ * spectrum 4 (4 n_b + band entries of D_b + 2 kdim[b]).  Reading synchronises
+ * the device. */
 int otlm_ragged_profile_enable(otlm_ragged r, int32_t on);
-int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count);
+int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count, int64_t* work);
 
 /* Release a plan.  NULL is a no-op.  Synchronises the device. */
 int otlm_ragged_free(otlm_ragged r);

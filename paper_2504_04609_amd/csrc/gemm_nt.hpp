@@ -58,9 +58,12 @@ __device__ __forceinline__ float half_wave_reduce(float v) {
 }
 
 // One BM x BN output tile at (m0, n0); `tile` is the column-tile index passed
-// to row_partial().  Shared by the plain and the grouped launches.
+// to row_partial().  Shared by the plain and the grouped launches.  With a row
+// index (rowidx != null) the tile's rows m0.. are positions in that list: A
+// row rowidx[m] is read and the epilogue sees row rowidx[m] (gathered rows).
 template <int BM, int BN, class Epi>
-__device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& epi, int m0, int n0, int tile) {
+__device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& epi, int m0, int n0, int tile,
+                                                 const int* __restrict__ rowidx = nullptr) {
   constexpr int BK = GEMM_BK, LD = GEMM_LDS_LD;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
   constexpr int A_V4 = BM * (BK / 4) / 256;
@@ -74,13 +77,16 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
   const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
 
   f32x4 ra[A_V4], rb[B_V4];
+  const float* arow[A_V4];  // A row of each staged chunk (null: beyond M)
+#pragma unroll
+  for (int q = 0; q < A_V4; ++q) {
+    const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = m0 + r;
+    arow[q] = gr < g.M ? g.A + (size_t)(rowidx ? rowidx[gr] : gr) * g.lda + c : nullptr;
+  }
   auto gload = [&](int kt) {
 #pragma unroll
-    for (int q = 0; q < A_V4; ++q) {
-      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = m0 + r;
-      ra[q] = gr < g.M ? *reinterpret_cast<const f32x4*>(g.A + (size_t)gr * g.lda + kt * BK + c)
-                       : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int q = 0; q < A_V4; ++q)
+      ra[q] = arow[q] ? *reinterpret_cast<const f32x4*>(arow[q] + kt * BK) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < B_V4; ++q) {
       const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = n0 + r;
@@ -150,12 +156,13 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
     for (int r = 0; r < 16; ++r) {
       const int row = wm * WM + fm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
       const int m = m0 + row;
-      float red[2] = {Epi::RED_IS_MAX[0] ? 0.f : 0.f, 0.f};
+      float red[2] = {0.f, 0.f};
       if (m < g.M) {
+        const int mr = rowidx ? rowidx[m] : m;
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
           const int n = n0 + wn * WN + fn * 32 + l32;
-          if (n < g.N) epi.elem(m, n, acc[fm][fn][r], red);
+          if (n < g.N) epi.elem(mr, n, acc[fm][fn][r], red);
         }
       }
       if constexpr (Epi::NRED > 0) {
@@ -179,7 +186,7 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
           float v[2];
           v[0] = red_op<Epi::RED_IS_MAX[0]>(red_s[0][row][0], red_s[1][row][0]);
           v[1] = red_op<Epi::RED_IS_MAX[1]>(red_s[0][row][1], red_s[1][row][1]);
-          epi.row_partial(m, tile, v);
+          epi.row_partial(rowidx ? rowidx[m] : m, tile, v);
         }
       }
     }
@@ -204,6 +211,7 @@ struct GemmGroups {
   int ngroups;
   int tile0[GEMM_MAX_GROUPS + 1];
   int ntn[GEMM_MAX_GROUPS];
+  int nvalid[GEMM_MAX_GROUPS];  // unpadded N = Kd of the group (work count only)
   GemmArgs g[GEMM_MAX_GROUPS];
   Epi epi[GEMM_MAX_GROUPS];
 };
@@ -216,4 +224,37 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_grouped(GemmGroups<Epi> p) {
   for (int i = 1; i < GEMM_MAX_GROUPS; ++i) q += (i < p.ngroups && L >= p.tile0[i]) ? 1 : 0;
   const int t = L - p.tile0[q], tm = t / p.ntn[q], tn = t - tm * p.ntn[q];
   gemm_nt_f32_tile<BM, BN, Epi>(p.g[q], p.epi[q], tm * BM, tn * BN, tn);
+}
+
+// Active rows of a grouped product, rebuilt on the device between launches:
+// group q multiplies only the nact[q] rows listed at rows[row0[q]..] (row
+// numbers inside the group), in tiles tile0[q] .. tile0[q+1] - 1 of the grid.
+// The grid is sized for every row; workgroups past tile0[ngroups] exit.
+struct GemmActive {
+  int nact[GEMM_MAX_GROUPS];
+  int row0[GEMM_MAX_GROUPS];
+  int tile0[GEMM_MAX_GROUPS + 1];
+};
+
+// work (nullable): the launch adds its algorithmic multiply-adds,
+// sum_q nact[q] nvalid[q]^2, for profiling.
+template <int BM, int BN, class Epi>
+__global__ __launch_bounds__(256) void gemm_nt_f32_grouped_active(GemmGroups<Epi> p, const GemmActive* __restrict__ act,
+                                                                  const int* __restrict__ rows,
+                                                                  unsigned long long* __restrict__ work) {
+  const int L = blockIdx.x;
+  if (work && L == 0 && threadIdx.x == 0) {
+    unsigned long long macs = 0;
+    for (int q = 0; q < p.ngroups; ++q)
+      macs += (unsigned long long)act->nact[q] * (unsigned long long)p.nvalid[q] * (unsigned long long)p.nvalid[q];
+    atomicAdd(work, macs);
+  }
+  if (L >= act->tile0[p.ngroups]) return;
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < GEMM_MAX_GROUPS; ++i) q += (i < p.ngroups && L >= act->tile0[i]) ? 1 : 0;
+  const int t = L - act->tile0[q], tm = t / p.ntn[q], tn = t - tm * p.ntn[q];
+  GemmArgs g = p.g[q];
+  g.M = act->nact[q];
+  gemm_nt_f32_tile<BM, BN, Epi>(g, p.epi[q], tm * BM, tn * BN, tn, rows + act->row0[q]);
 }

@@ -37,6 +37,11 @@ struct otlm_ragged_s {
   RgSpec* spec = nullptr;
   float *V = nullptr, *S = nullptr, *A = nullptr, *U = nullptr, *Yg = nullptr, *Wst = nullptr, *DT = nullptr;
   float* Wsnap = nullptr;  // weights at the previous convergence test
+  GemmActive* act = nullptr;  // active rows of the grouped products (device)
+  int* nband = nullptr;       // band entries of each spectrum's dictionary
+  unsigned long long* work = nullptr;  // profiling: [0] kernel-product MACs, [1] weight-step bytes
+  int* act_rows = nullptr;
+  RgGroups gi{};
   float4* colc = nullptr;
   int2* band = nullptr;
   float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr, *ew_prev = nullptr, *ew_best = nullptr;
@@ -137,6 +142,7 @@ GemmGroups<Epi> rg_groups(const otlm_ragged_s* r, int bm, int bn, bool transpose
     const auto& G = r->grp[g];
     const int ntm = (G.rows + bm - 1) / bm, ntn = (G.np + bn - 1) / bn;
     gg.ntn[g] = ntn;
+    gg.nvalid[g] = G.n;
     gg.g[g] = GemmArgs{Aop + G.base, G.np, transposed ? G.K->KT : G.K->K, G.np, G.rows, G.np, G.np};
     gg.epi[g] = mk(g);
     t += ntm * ntn;
@@ -145,22 +151,31 @@ GemmGroups<Epi> rg_groups(const otlm_ragged_s* r, int bm, int bn, bool transpose
   return gg;
 }
 
+// Grouped product over the active rows; the grid covers every row and the
+// workgroups beyond the active tiles exit.
 template <class Epi>
-void rg_launch(int tile, const GemmGroups<Epi>& gg, hipStream_t s) {
+void rg_launch(const otlm_ragged_s* r, int tile, const GemmGroups<Epi>& gg, hipStream_t s) {
   const dim3 grid((unsigned)gg.tile0[GEMM_MAX_GROUPS]), block(256);
+  unsigned long long* work = r->profile ? r->work : nullptr;
   if (tile == 0) {
-    auto kern = gemm_nt_f32_grouped<128, 128, Epi>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, gg);
+    auto kern = gemm_nt_f32_grouped_active<128, 128, Epi>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, gg, (const GemmActive*)r->act, (const int*)r->act_rows, work);
   } else if (tile == 1) {
-    auto kern = gemm_nt_f32_grouped<128, 64, Epi>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, gg);
+    auto kern = gemm_nt_f32_grouped_active<128, 64, Epi>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, gg, (const GemmActive*)r->act, (const int*)r->act_rows, work);
   } else if (tile == 2) {
-    auto kern = gemm_nt_f32_grouped<64, 128, Epi>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, gg);
+    auto kern = gemm_nt_f32_grouped_active<64, 128, Epi>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, gg, (const GemmActive*)r->act, (const int*)r->act_rows, work);
   } else {
-    auto kern = gemm_nt_f32_grouped<64, 64, Epi>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, gg);
+    auto kern = gemm_nt_f32_grouped_active<64, 64, Epi>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, gg, (const GemmActive*)r->act, (const int*)r->act_rows, work);
   }
+}
+
+// Rebuild the active-row lists for tile shape `tile` from the done flags.
+void rg_compact_rows(otlm_ragged_s* r, int tile, hipStream_t s) {
+  hipLaunchKernelGGL(rg_compact, dim3(1), dim3(1024), 0, s, (const int*)r->done, r->gi, RG_TILES[tile][0],
+                     RG_TILES[tile][1], r->act, r->act_rows);
 }
 
 void rg_product_s(otlm_ragged_s* r, int tile, bool chk, hipStream_t s) {
@@ -169,7 +184,7 @@ void rg_product_s(otlm_ragged_s* r, int tile, bool chk, hipStream_t s) {
     return EpiSrc{r->S + G.base, nullptr, r->A + G.base, r->U + G.base, r->psn + G.row0 * r->ts,
                   r->psd + G.row0 * r->ts, G.np, G.n, r->ts, chk};
   });
-  rg_launch(tile, gg, s);
+  rg_launch(r, tile, gg, s);
 }
 
 void rg_product_t(otlm_ragged_s* r, int tile, hipStream_t s) {
@@ -177,7 +192,7 @@ void rg_product_t(otlm_ragged_s* r, int tile, hipStream_t s) {
     const auto& G = r->grp[g];
     return EpiProx{r->V + G.base, r->Yg + G.base, r->done + G.row0, r->pc, G.np, G.np, G.n, false, nullptr};
   });
-  rg_launch(tile, gg, s);
+  rg_launch(r, tile, gg, s);
 }
 
 // One outer iteration of Algorithm 1 over the whole ragged batch.
@@ -190,7 +205,7 @@ void rg_iterate(otlm_ragged_s* r, bool chk, hipStream_t s) {
     RgProfScope ps(r, RG_PROF_W, s);
     hipLaunchKernelGGL(rg_weight_step, dim3((unsigned)r->B), dim3(RG_THREADS), 3 * (size_t)r->npmax * sizeof(float),
                        s, r->spec, r->DT, r->colc, r->band, r->p.pen, r->p.inner_max, r->S, r->A, r->U, r->Wst,
-                       r->done);
+                       r->done, (const int*)r->nband, r->profile ? r->work + 1 : nullptr);
   }
   {
     RgProfScope ps(r, RG_PROF_KTU, s);
@@ -199,7 +214,8 @@ void rg_iterate(otlm_ragged_s* r, bool chk, hipStream_t s) {
 }
 
 // One check interval: c iterations, the last one accumulating the convergence
-// partials, then the convergence test (when a tolerance is set).
+// partials, then the convergence test (when a tolerance is set) and the new
+// active-row lists.
 void rg_chunk(otlm_ragged_s* r, int c, hipStream_t s) {
   const bool test = r->p.tol > 0.0;
   hipLaunchKernelGGL(rg_advance, dim3(1), dim3(64), 0, s, r->it_dev, c);
@@ -211,6 +227,7 @@ void rg_chunk(otlm_ragged_s* r, int c, hipStream_t s) {
     hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, r->psn, r->psd, r->ts, r->pwn, r->pwd,
                        (int)r->B, (float)r->p.tol, OTLM_FP32_FLOOR, 0, r->ew_prev, r->ew_best, r->stall, r->done,
                        r->iters, r->status, r->flags, r->it_dev);
+    rg_compact_rows(r, r->tile, s);
   }
 }
 
@@ -224,6 +241,7 @@ int rg_autotune(otlm_ragged_s* r, int forced, hipStream_t s) {
   OTLM_HIP(hipEventCreate(&e1));
   int best = 0;
   for (int t = 0; t < 4; ++t) {
+    rg_compact_rows(r, t, s);
     rg_product_s(r, t, false, s);
     (void)hipEventRecord(e0, s);
     for (int rep = 0; rep < 3; ++rep) rg_product_s(r, t, false, s);
@@ -334,11 +352,15 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
     const otlm_kernel_s* K = kernels[order[g]];
     group_of_kernel[order[g]] = g;
     r->grp[g] = {K, (int)K->n, (int)K->np, (int)used[order[g]], row0, base};
+    r->gi.row0[g] = (int)row0;
+    r->gi.rows[g] = (int)used[order[g]];
+    r->gi.np[g] = (int)K->np;
     row0 += used[order[g]];
     base += used[order[g]] * K->np;
     r->npmax = std::max(r->npmax, (int)K->np);
   }
   r->tot_state = base;
+  r->gi.ngroups = r->ngroups;
   r->ts = (r->npmax + 63) / 64;
   // offsets of the packed inputs (input order)
   std::vector<int64_t> yin(B), din(B), win(B);
@@ -389,7 +411,8 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
             r->alloc(&r->band, r->tot_cols) && r->alloc(&r->psn, B * r->ts) && r->alloc(&r->psd, B * r->ts) &&
             r->alloc(&r->pwn, B) && r->alloc(&r->pwd, B) && r->alloc(&r->ew_prev, B) && r->alloc(&r->ew_best, B) &&
             r->alloc(&r->done, B) && r->alloc(&r->iters, B) && r->alloc(&r->status, B) && r->alloc(&r->flags, 4) &&
-            r->alloc(&r->stall, B) && r->alloc(&r->it_dev, 1);
+            r->alloc(&r->stall, B) && r->alloc(&r->it_dev, 1) && r->alloc(&r->act, 1) &&
+            r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 2);
   if (!ok) return fail(OTLM_E_NOMEM);
   if (hipHostMalloc((void**)&r->host_flags, 4 * sizeof(int)) != hipSuccess) return fail(OTLM_E_NOMEM);
   const size_t sb = (size_t)r->tot_state * sizeof(float);
@@ -422,12 +445,13 @@ int otlm_ragged_solve(otlm_ragged r, const float* D, const float* Y, float* W, f
   OTLM_HIP(hipMemsetAsync(r->flags, 0, 4 * sizeof(int), s));
   OTLM_HIP(hipMemsetAsync(r->it_dev, 0, sizeof(int), s));
   hipLaunchKernelGGL(rg_prep_dict, dim3((unsigned)r->B), dim3(RG_THREADS), 0, s, r->spec, D, p.pen, p.eps, p.alpha,
-                     p.beta, r->DT, r->colc, r->band, r->flags + 1);
+                     p.beta, r->DT, r->colc, r->band, r->nband, r->flags + 1);
   hipLaunchKernelGGL(rg_init, dim3((unsigned)r->B), dim3(RG_THREADS), (size_t)r->npmax * sizeof(float), s, r->spec, Y,
                      (const float*)W, (const float*)logV, r->DT, r->colc, r->band, p.warm, r->Yg, r->V, r->U, r->A,
                      r->Wst, r->done, r->status, r->iters, r->ew_prev, r->ew_best, r->stall, r->flags + 1);
   hipLaunchKernelGGL(rg_interval_change, dim3((unsigned)((r->B + 3) / 4)), dim3(256), 0, s, r->spec, (int)r->B, r->Wst,
                      r->Wsnap, 1, r->pwn, r->pwd);
+  rg_compact_rows(r, r->tile, s);
   OTLM_HIP(hipGetLastError());
   OTLM_HIP(hipMemcpyAsync(r->host_flags, r->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   OTLM_HIP(hipStreamSynchronize(s));
@@ -472,6 +496,7 @@ int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* 
 int otlm_ragged_profile_enable(otlm_ragged r, int32_t on) {
   if (!r) return OTLM_E_INVALID;
   rg_prof_collect(r);
+  OTLM_HIP(hipMemset(r->work, 0, 2 * sizeof(unsigned long long)));
   for (int c = 0; c < RG_PROF_CLASSES; ++c) {
     r->prof_ms[c] = 0.0;
     r->prof_n[c] = 0;
@@ -480,9 +505,16 @@ int otlm_ragged_profile_enable(otlm_ragged r, int32_t on) {
   return OTLM_OK;
 }
 
-int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count) {
+int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count, int64_t* work) {
   if (!r) return OTLM_E_INVALID;
   rg_prof_collect(r);
+  if (work) {
+    unsigned long long h[2] = {0, 0};
+    OTLM_HIP(hipDeviceSynchronize());
+    OTLM_HIP(hipMemcpy(h, r->work, sizeof(h), hipMemcpyDeviceToHost));
+    work[0] = (int64_t)h[0];
+    work[1] = (int64_t)h[1];
+  }
   for (int c = 0; c < RG_PROF_CLASSES; ++c) {
     if (ms) ms[c] = r->prof_n[c] ? r->prof_ms[c] / (double)r->prof_n[c] : 0.0;
     if (count) count[c] = r->prof_n[c];

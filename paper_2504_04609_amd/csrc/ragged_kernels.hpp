@@ -17,6 +17,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "omega.hpp"
+#include "gemm_nt.hpp"
 #include "solver_kernels.hpp"
 
 // One spectrum of a ragged solve, in solve order (groups of equal grid, the
@@ -71,12 +72,16 @@ __device__ __forceinline__ void rg_dict_apply(const float* __restrict__ DTb, con
 
 // Transposed copy of every D_b, the band of each column, and the per-column
 // constants of the weight step {1/x_j, shift_j, gamma_j, log gamma_j}
-// (x_j = sum_i D_ij, summed in FP64 in row order).  Flags negative or
-// non-finite entries and empty columns in bad[0].  One workgroup per spectrum.
+// (x_j = sum_i D_ij, summed in FP64 in row order); nband[q] = sum_j band
+// length.  Flags negative or non-finite entries and empty columns in bad[0].
+// One workgroup per spectrum.
 __global__ __launch_bounds__(RG_THREADS) void rg_prep_dict(const RgSpec* __restrict__ spec, const float* __restrict__ D,
                                                           int pen, double eps, double alpha, double beta,
                                                           float* __restrict__ DT, float4* __restrict__ colc,
-                                                          int2* __restrict__ band, int* __restrict__ bad) {
+                                                          int2* __restrict__ band, int* __restrict__ nband,
+                                                          int* __restrict__ bad) {
+  __shared__ int nb_s;
+  if (threadIdx.x == 0) nb_s = 0;
   const RgSpec sp = spec[blockIdx.x];
   const int n = sp.n, k = sp.k, ks = k | 1;  // odd LDS stride: conflict-free column reads
   __shared__ float tile[RG_TILE_ROWS * (RG_MAX_K + 1)];
@@ -120,8 +125,11 @@ __global__ __launch_bounds__(RG_THREADS) void rg_prep_dict(const RgSpec* __restr
     }
     colc[sp.col + j] = make_float4((float)(1.0 / x), (float)shift, (float)gam, (float)log(gam));
     band[sp.col + j] = make_int2(lo < hi ? lo : 0, lo < hi ? hi : 0);
+    if (lo < hi) atomicAdd(&nb_s, hi - lo);
     if (badl) bad[0] = 1;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) nband[blockIdx.x] = nb_s;
 }
 
 // Per-spectrum start: y copied into the group layout (zero padded), the
@@ -202,10 +210,14 @@ __global__ __launch_bounds__(RG_THREADS) void rg_weight_step(const RgSpec* __res
                                                             const int2* __restrict__ band, int pen, int inner,
                                                             const float* __restrict__ S, float* __restrict__ A,
                                                             float* __restrict__ U, float* __restrict__ Wst,
-                                                            const int* __restrict__ done) {
+                                                            const int* __restrict__ done,
+                                                            const int* __restrict__ nband,
+                                                            unsigned long long* __restrict__ work) {
   const int q = blockIdx.x;
   if (done[q]) return;
   const RgSpec sp = spec[q];
+  if (work && threadIdx.x == 0)  // algorithmic bytes: s, a in; a, u out; the band of D once; w in and out
+    atomicAdd(work, 4ull * (4ull * sp.n + (unsigned long long)nband[q] + 2ull * sp.k));
   const int n = sp.n, k = sp.k, np = sp.np;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   extern __shared__ float sm[];
@@ -297,6 +309,59 @@ __global__ __launch_bounds__(256) void rg_interval_change(const RgSpec* __restri
   if (lane == 0 && !init) {
     pwn[q] = (float)dw;
     pwd[q] = (float)wm;
+  }
+}
+
+// Static description of the groups for the active-row compaction.
+struct RgGroups {
+  int ngroups;
+  int row0[GEMM_MAX_GROUPS];  // first spectrum of the group (solve order)
+  int rows[GEMM_MAX_GROUPS];  // spectra in the group
+  int np[GEMM_MAX_GROUPS];    // row stride = GEMM N
+};
+
+// Active-row lists of the grouped products, rebuilt after every convergence
+// test: for group g the rows (group-relative, ascending) of the spectra not
+// yet stopped go to rows[row0_g ...], their count to act->nact[g], and the
+// grid offsets of the group's BM x BN tiles to act->tile0.  Stable wave-ballot
+// compaction in chunks of 1024 rows.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void rg_compact(const int* __restrict__ done, RgGroups gi, int bm, int bn,
+                                                  GemmActive* __restrict__ act, int* __restrict__ rows) {
+  __shared__ int wsum[16];
+  __shared__ int nact_s[GEMM_MAX_GROUPS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int g = 0; g < gi.ngroups; ++g) {
+    int base = 0;
+    for (int c0 = 0; c0 < gi.rows[g]; c0 += 1024) {
+      const int r = c0 + tid;
+      const bool on = r < gi.rows[g] && !done[gi.row0[g] + r];
+      const unsigned long long m = __ballot(on);
+      const int before = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wsum[wave] = __popcll(m);
+      __syncthreads();
+      int off = 0, tot = 0;
+      for (int w = 0; w < 16; ++w) {
+        off += w < wave ? wsum[w] : 0;
+        tot += wsum[w];
+      }
+      if (on) rows[gi.row0[g] + base + off + before] = r;
+      base += tot;
+      __syncthreads();
+    }
+    if (tid == 0) nact_s[g] = base;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int t = 0;
+    for (int g = 0; g < GEMM_MAX_GROUPS; ++g) {
+      act->tile0[g] = t;
+      const bool used = g < gi.ngroups;
+      const int na = used ? nact_s[g] : 0;
+      act->nact[g] = na;
+      act->row0[g] = used ? gi.row0[g] : 0;
+      if (used) t += ((na + bm - 1) / bm) * ((gi.np[g] + bn - 1) / bn);
+    }
+    act->tile0[GEMM_MAX_GROUPS] = t;
   }
 }
 

@@ -82,7 +82,7 @@ def load() -> ctypes.CDLL:
     lib.otlm_ragged_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(f64), ctypes.POINTER(i64)]
     lib.otlm_ragged_profile_enable.argtypes = [vp, ctypes.c_int32]
-    lib.otlm_ragged_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+    lib.otlm_ragged_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.otlm_ragged_free.argtypes = [vp]
     for name in ("otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info", "otlm_solve_batch", "otlm_objective",
                  "otlm_profile_enable", "otlm_profile_read", "otlm_ragged_create", "otlm_ragged_solve",
@@ -286,8 +286,11 @@ class RaggedPlan:
     def profile_read(self):
         ms = (ctypes.c_double * len(RAGGED_PROFILE_CLASSES))()
         cnt = (ctypes.c_int64 * len(RAGGED_PROFILE_CLASSES))()
-        _check(load().otlm_ragged_profile_read(self.handle, ms, cnt), "otlm_ragged_profile_read")
-        return {name: (ms[i], cnt[i]) for i, name in enumerate(RAGGED_PROFILE_CLASSES)}
+        work = (ctypes.c_int64 * 2)()
+        _check(load().otlm_ragged_profile_read(self.handle, ms, cnt, work), "otlm_ragged_profile_read")
+        out = {name: (ms[i], cnt[i]) for i, name in enumerate(RAGGED_PROFILE_CLASSES)}
+        out["product_macs"], out["weight_step_bytes"] = work[0], work[1]
+        return out
 
     def solve(self, D, Y, W=None, logV=None, want_logU=True, stream=None):
         """otlm_ragged_solve on packed CUDA tensors D [sum n_b k_b], Y [sum n_b].
