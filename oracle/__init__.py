@@ -7,3 +7,4 @@ from .otlm_oracle import *  # noqa: F401,F403
 from .otlm_oracle import (omega, gibbs_kernel, prox_datafit, mm_step, prox_P_exact,  # noqa: F401
                           prox_objective, penalty_value, penalty_grad, initial_weights,
                           solve, objective)
+from . import mlp_oracle as mlp  # noqa: F401,E402
