@@ -79,8 +79,10 @@ enum {
   OTLM_S_CONVERGED = 1,   /* the stopping test passed                                */
   OTLM_S_MAX_ITER = 2,    /* stopped at the iteration cap                            */
   OTLM_S_NONFINITE = 4,   /* a NaN/Inf appeared; the spectrum was frozen             */
-  OTLM_S_STAGNATED = 8    /* the weight change stopped improving for 6 tests: the
+  OTLM_S_STAGNATED = 8,   /* the weight change stopped improving for 6 tests: the
                              noise floor of the phase precision was reached        */
+  OTLM_S_FALLBACK = 16    /* (with another flag) the warm start failed the probe
+                             and the spectrum was solved from the cold start       */
 };
 
 /* Solver parameters.  A solve has a bulk phase in precision `prec` and, when
@@ -102,6 +104,11 @@ typedef struct {
   double beta;           /* quadratic weight of OTLM_PEN_ELASTIC, > 0 there        */
   double tol;            /* final stopping tolerance, >= 0 (0 = run to the caps)   */
   double bulk_tol;       /* bulk-phase tolerance when a refinement follows, >= 0   */
+  double warm_probe;     /* > 0 with warm = 1: at the first convergence test, a
+                            spectrum whose weight change over the interval
+                            exceeds warm_probe relative to max|w| (or is not
+                            finite) restarts from the cold start and is flagged
+                            OTLM_S_FALLBACK; 0: no probe                          */
   int32_t max_iter;      /* iteration cap of the bulk phase, >= 1                  */
   int32_t check_every;   /* convergence test cadence in iterations, >= 1           */
   int32_t fit;           /* otlm_datafit                                           */
@@ -295,6 +302,70 @@ int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count, int64_t*
 
 /* Release a plan.  NULL is a no-op.  Synchronises the device. */
 int otlm_ragged_free(otlm_ragged r);
+
+/* ---------------------------------------------------------------------------
+ * Warm-start network (not part of the paper): a multilayer perceptron
+ *   x -> GELU(x W1^T + b1) -> GELU(. W2^T + b2) -> . W3^T + b3
+ * (exact erf GELU, weights [out, in] row-major, flat parameter vector
+ * [W1, b1, W2, b2, W3, b3]) that maps a target spectrum y to a starting point
+ * of Algorithm 1, the (log u, log v, w) the solver reaches for it.  Inputs are
+ * standardised per feature and targets per output (after clamping to
+ * [-50, 50]) with statistics of the training set; the loss is the mean squared
+ * error of the standardised outputs.  Trained by AdamW on minibatches of a
+ * training set held in device memory; FP32 training, FP32 or BF16 inference.
+ * ------------------------------------------------------------------------- */
+typedef struct otlm_mlp_s* otlm_mlp;
+
+typedef struct {
+  double lr;            /* learning rate, >= 0                       */
+  double beta1, beta2;  /* moment decays, in [0, 1)                  */
+  double eps;           /* > 0                                       */
+  double weight_decay;  /* decoupled decay on every parameter, >= 0  */
+} otlm_adamw;
+
+/* Create a network with layer widths dims[4] = {in, h1, h2, out} (in, h1, h2
+ * multiples of 32; out a multiple of 16) and initial parameters theta (host or
+ * device FP32, [nparam], copied).  Standardisation starts as the identity.
+ * Synchronises `stream`.  Errors: OTLM_E_INVALID, OTLM_E_NOMEM, OTLM_E_HIP. */
+int otlm_mlp_create(const int32_t* dims, const float* theta, void* stream, otlm_mlp* out);
+
+/* Layer widths, parameter count and AdamW steps taken (any may be NULL). */
+int otlm_mlp_info(otlm_mlp m, int32_t* dims, int64_t* nparam, int64_t* step);
+
+/* Set the standardisation from a training set: X device FP32 [N, in] (raw
+ * targets y), T device FP32 [N, out] (raw outputs, clamped to [-50, 50]);
+ * per column mean and standard deviation (floored at 1e-6), FP64 sums.
+ * Synchronises `stream`. */
+int otlm_mlp_set_norm(otlm_mlp m, const float* X, const float* T, int64_t N, void* stream);
+
+/* Copy the standardisation statistics out (any pointer may be NULL). */
+int otlm_mlp_get_norm(otlm_mlp m, float* in_mu, float* in_sd, float* out_mu, float* out_sd, void* stream);
+
+/* Gradient of the loss on the minibatch of rows idx[0..B) (device int32) of X
+ * [*, in] and T [*, out] (B a multiple of 16): grad device FP32 [nparam]
+ * (may be NULL), loss device FP32 [1] (may be NULL).  No parameter update. */
+int otlm_mlp_grad(otlm_mlp m, const float* X, const float* T, const int32_t* idx, int64_t B,
+                  float* grad, float* loss, void* stream);
+
+/* One AdamW step on the minibatch (as otlm_mlp_grad, then the update). */
+int otlm_mlp_train_step(otlm_mlp m, const float* X, const float* T, const int32_t* idx, int64_t B,
+                        const otlm_adamw* h, float* loss, void* stream);
+
+/* Copy the parameters out / in (device or host FP32 [nparam]). */
+int otlm_mlp_get_params(otlm_mlp m, float* theta, void* stream);
+int otlm_mlp_set_params(otlm_mlp m, const float* theta, void* stream);
+
+/* Predict starting points for B raw targets Y (device FP32 [B, in]) in
+ * precision prec (OTLM_PREC_FP32, or OTLM_PREC_BF16: BF16 weights and
+ * activations, FP32 accumulation).  The outputs are split by column: the first
+ * n_u into logU [B, n_u] (may be NULL), the next n_v into logV [B, n_v], the
+ * rest into W [B, out - n_u - n_v], clamped to >= 0, so logV and W can be
+ * passed to otlm_solve_batch with warm = 1. */
+int otlm_mlp_infer(otlm_mlp m, const float* Y, int64_t B, int32_t prec, int32_t n_u, int32_t n_v,
+                   float* logU, float* logV, float* W, void* stream);
+
+/* Release the network.  NULL is a no-op.  Synchronises the device. */
+int otlm_mlp_free(otlm_mlp m);
 
 /* Static description of an otlm_status code. */
 const char* otlm_status_str(int code);

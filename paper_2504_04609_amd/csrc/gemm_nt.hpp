@@ -61,7 +61,14 @@ __device__ __forceinline__ float half_wave_reduce(float v) {
 // to row_partial().  Shared by the plain and the grouped launches.  With a row
 // index (rowidx != null) the tile's rows m0.. are positions in that list: A
 // row rowidx[m] is read and the epilogue sees row rowidx[m] (gathered rows).
-template <int BM, int BN, class Epi>
+//
+// Layouts: by default both operands are k-contiguous (A [M, Kd], Bt [N, Kd]).
+// TA = true reads A stored [Kd, M] (element (m, k) at A[k * lda + m]) and
+// TB = true reads B stored [Kd, N] (element (n, k) at Bt[k * ldb + n]); such
+// operands are loaded 4 consecutive m (or n) at a time and transposed into the
+// same LDS layout, so the MFMA core is shared.  Those layouts need M (resp. N)
+// a multiple of 4 and take no row index.
+template <int BM, int BN, class Epi, bool TA = false, bool TB = false>
 __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& epi, int m0, int n0, int tile,
                                                  const int* __restrict__ rowidx = nullptr) {
   constexpr int BK = GEMM_BK, LD = GEMM_LDS_LD;
@@ -78,32 +85,57 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
 
   f32x4 ra[A_V4], rb[B_V4];
   const float* arow[A_V4];  // A row of each staged chunk (null: beyond M)
+  if constexpr (!TA) {
 #pragma unroll
-  for (int q = 0; q < A_V4; ++q) {
-    const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = m0 + r;
-    arow[q] = gr < g.M ? g.A + (size_t)(rowidx ? rowidx[gr] : gr) * g.lda + c : nullptr;
+    for (int q = 0; q < A_V4; ++q) {
+      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = m0 + r;
+      arow[q] = gr < g.M ? g.A + (size_t)(rowidx ? rowidx[gr] : gr) * g.lda + c : nullptr;
+    }
   }
+  constexpr f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   auto gload = [&](int kt) {
 #pragma unroll
-    for (int q = 0; q < A_V4; ++q)
-      ra[q] = arow[q] ? *reinterpret_cast<const f32x4*>(arow[q] + kt * BK) : f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < A_V4; ++q) {
+      if constexpr (!TA) {
+        ra[q] = arow[q] ? *reinterpret_cast<const f32x4*>(arow[q] + kt * BK) : zero4;
+      } else {
+        const int idx = tid + q * 256, kr = idx / (BM / 4), mc = (idx % (BM / 4)) * 4, gm = m0 + mc;
+        ra[q] = gm < g.M ? *reinterpret_cast<const f32x4*>(g.A + (size_t)(kt * BK + kr) * g.lda + gm) : zero4;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < B_V4; ++q) {
-      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = n0 + r;
-      rb[q] = gr < g.N ? *reinterpret_cast<const f32x4*>(g.Bt + (size_t)gr * g.ldb + kt * BK + c)
-                       : f32x4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (!TB) {
+        const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4, gr = n0 + r;
+        rb[q] = gr < g.N ? *reinterpret_cast<const f32x4*>(g.Bt + (size_t)gr * g.ldb + kt * BK + c) : zero4;
+      } else {
+        const int idx = tid + q * 256, kr = idx / (BN / 4), nc = (idx % (BN / 4)) * 4, gn = n0 + nc;
+        rb[q] = gn < g.N ? *reinterpret_cast<const f32x4*>(g.Bt + (size_t)(kt * BK + kr) * g.ldb + gn) : zero4;
+      }
     }
   };
   auto swrite = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < A_V4; ++q) {
-      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
-      *reinterpret_cast<f32x4*>(&As[buf][r * LD + c]) = ra[q];
+      if constexpr (!TA) {
+        const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
+        *reinterpret_cast<f32x4*>(&As[buf][r * LD + c]) = ra[q];
+      } else {
+        const int idx = tid + q * 256, kr = idx / (BM / 4), mc = (idx % (BM / 4)) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) As[buf][(mc + j) * LD + kr] = ra[q][j];
+      }
     }
 #pragma unroll
     for (int q = 0; q < B_V4; ++q) {
-      const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
-      *reinterpret_cast<f32x4*>(&Bs[buf][r * LD + c]) = rb[q];
+      if constexpr (!TB) {
+        const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 4;
+        *reinterpret_cast<f32x4*>(&Bs[buf][r * LD + c]) = rb[q];
+      } else {
+        const int idx = tid + q * 256, kr = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bs[buf][(nc + j) * LD + kr] = rb[q][j];
+      }
     }
   };
 
@@ -196,6 +228,12 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
 template <int BM, int BN, class Epi>
 __global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
   gemm_nt_f32_tile<BM, BN, Epi>(g, epi, blockIdx.y * BM, blockIdx.x * BN, blockIdx.x);
+}
+
+// Any of the four operand layouts (see gemm_nt_f32_tile).
+template <int BM, int BN, bool TA, bool TB, class Epi>
+__global__ __launch_bounds__(256) void gemm_f32_layout(GemmArgs g, Epi epi) {
+  gemm_nt_f32_tile<BM, BN, Epi, TA, TB>(g, epi, blockIdx.y * BM, blockIdx.x * BN, blockIdx.x);
 }
 
 // Grouped launch: up to GEMM_MAX_GROUPS independent products (each with its

@@ -26,6 +26,7 @@
 #include "objective_kernels.hpp"
 #include "prox_newton.hpp"
 #include "ragged_kernels.hpp"
+#include "mlp_kernels.hpp"
 #include "solver_kernels.hpp"
 #include "solver_kernels64.hpp"
 
@@ -54,6 +55,8 @@ struct Workspace {
   float* ew_best = nullptr;
   int* stall = nullptr;
   int* nit = nullptr;
+  int* mm_until = nullptr;  // last iteration of each spectrum's MM warm-up (exact weight prox)
+  int* fallback = nullptr;  // 1 when a warm start was replaced by the cold start
   unsigned short *Vbf = nullptr, *Ubf = nullptr;
   // FP64 refinement state
   int64_t B64 = 0;
@@ -78,6 +81,7 @@ struct Workspace {
     ew_best = nullptr;
     stall = nullptr;
     nit = nullptr;
+    mm_until = fallback = nullptr;
     Vbf = Ubf = nullptr;
   }
   void release64() {
@@ -179,6 +183,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.ew_best, (size_t)B);
   rc |= dev_alloc(ws, &ws.stall, (size_t)B);
   rc |= dev_alloc(ws, &ws.nit, (size_t)B);
+  rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
+  rc |= dev_alloc(ws, &ws.fallback, (size_t)B);
   rc |= dev_alloc(ws, &ws.Vbf, bn);
   rc |= dev_alloc(ws, &ws.Ubf, bn);
   if (rc != OTLM_OK) {
@@ -264,7 +270,7 @@ bool params_valid(const otlm_params* p, double kernel_eps) {
   if (p->prec != OTLM_PREC_FP32 && p->prec != OTLM_PREC_BF16) return false;
   if (p->refine < OTLM_REFINE_NONE || p->refine > OTLM_REFINE_FP64) return false;
   if (p->refine != OTLM_REFINE_NONE && p->refine_sweeps < 1) return false;
-  if (!(p->bulk_tol >= 0.0)) return false;
+  if (!(p->bulk_tol >= 0.0) || !(p->warm_probe >= 0.0)) return false;
   return true;
 }
 
@@ -472,7 +478,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
                      p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
                      (const float4*)ws.colc, (int)n, (int)kdim, (int)np, (int)kp, p->warm, ws.V, ws.W, ws.U,
-                     ws.done, ws.status, ws.iters, ws.ew_prev, ws.ew_best, ws.stall, ws.flags + 1);
+                     ws.done, ws.status, ws.iters, ws.ew_prev, ws.ew_best, ws.stall, ws.mm_until,
+                     exact ? OTLM_MM_WARMUP : 0, ws.fallback, ws.flags + 1);
   OTLM_HIP(hipGetLastError());
   OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   OTLM_HIP(hipStreamSynchronize(s));
@@ -505,6 +512,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   auto prox_args32 = [&]() {
     ProxNewtonArgs<float, float> a;
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
+    a.mm_until = ws.mm_until; a.it = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
     a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
@@ -514,15 +522,19 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   auto prox_args64 = [&]() {
     ProxNewtonArgs<double, double> a;
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
+    a.mm_until = nullptr; a.it = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit;
     return a;
   };
 
+  // Last iteration at which some spectrum still takes the MM step in the exact
+  // mode (cold starts: OTLM_MM_WARMUP; warm starts: none; a fallback restarts it).
+  int mm_until_max = (exact && !p->warm) ? OTLM_MM_WARMUP : 0;
   // One FP32 iteration (bulk phase or FP32 refinement); `it` counts from 1 over the whole solve.
   auto iterate32 = [&](int it, bool chk, bool bf16) {
-    const bool mm_step = !exact || it <= OTLM_MM_WARMUP;
+    const bool mm_step = !exact || it <= mm_until_max;
     {  // s = K v, r = log(s / a)
       EpiSrc e{ws.S, mm_step ? ws.R : nullptr, ws.A, ws.U, ws.psn, ws.psd, (int)np, (int)n, nts, chk};
       if (bf16) {
@@ -536,15 +548,17 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
         gemm(bm_k, bn_k, g, e, s);
       }
     }
-    if (!mm_step) {  // weight prox solved by active-set Newton
+    if (exact) {  // weight prox solved by active-set Newton (spectra past their MM warm-up)
       ProfScope ps(k, PROF_W32, s);
       auto kern = prox_newton_kernel<float, float>;
-      hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
-                         prox_newton_smem((int)n, sizeof(float)), s, prox_args32());
-    } else {  // MM weight step
+      auto a = prox_args32();
+      a.it = it;
+      hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS), prox_newton_smem((int)n, sizeof(float)), s, a);
+    }
+    if (mm_step) {  // MM weight step (every spectrum, or those in their warm-up)
       ProfScope ps(k, PROF_W32, s);
       GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
-      EpiWupd e{ws.W, ws.colc, ws.done, (int)kp, (int)kdim, p->pen, false};
+      EpiWupd e{ws.W, ws.colc, ws.done, exact ? ws.mm_until : nullptr, it, (int)kp, (int)kdim, p->pen, false};
       gemm(64, bn_w, g, e, s);
     }
     {  // a = D w, u = a / s
@@ -609,9 +623,12 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W, (int)kp, (int)kdim, M, ws.Wsnap, init, ws.pwn, ws.pwd);
     }
   };
-  auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase) -> int {
+  // probe: test the warm start at the first convergence test of this phase
+  auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase,
+                       bool probe) -> int {
     int it = it0;
     if (tol > 0.0) weight_change(use64, 1);
+    bool first_check = true;
     for (int j = 1; j <= cap; ++j) {
       it = it0 + j;
       const bool chk = (tol > 0.0) && (j % p->check_every == 0 || j == cap);
@@ -625,10 +642,25 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
                              M, (float)tol, floor_w, it, ws.ew_prev, ws.ew_best, ws.stall, ws.done, ws.iters,
                              ws.status, ws.flags, nullptr);
         }
+        const bool fb = probe && first_check;
+        if (fb)
+          hipLaunchKernelGGL(warm_fallback, dim3((unsigned)B), dim3(256), 0, s, (const float*)ws.pwn,
+                             (const float*)ws.pwd, (float)p->warm_probe, Y, (const float4*)ws.colc, (int)n,
+                             (int)kdim, (int)np, (int)kp, it, exact ? OTLM_MM_WARMUP : 0, ws.V,
+                             bf16 ? ws.Vbf : nullptr, ws.W, ws.Wsnap, ws.U, ws.done, ws.status, ws.ew_prev,
+                             ws.ew_best, ws.stall, ws.mm_until, ws.fallback, ws.flags + 2);
+        first_check = false;
         if (hipGetLastError() != hipSuccess) return OTLM_E_HIP;
-        if (hipMemcpyAsync(ws.host_flags, ws.flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipMemcpyAsync(ws.host_flags, ws.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
           return OTLM_E_HIP;
+        if (fb && ws.host_flags[2] > 0) {  // restarted spectra: a = D w0, and their MM warm-up
+          GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
+          EpiStore e{ws.A, (int)np, (int)n, false};
+          gemm(64, 128, g, e, s);
+          if (exact) mm_until_max = it + OTLM_MM_WARMUP;
+          continue;
+        }
         if (ws.host_flags[0] == 0) break;
       }
     }
@@ -641,8 +673,9 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     hipLaunchKernelGGL(convert_f32_to_bf16, dim3(1024), dim3(256), 0, s, ws.V, ws.Vbf, (size_t)B * np);
     OTLM_HIP(hipGetLastError());
   }
+  const bool probe = p->warm && p->warm_probe > 0.0;
   int last = run_phase(0, p->max_iter, refine ? p->bulk_tol : p->tol, bulk_bf16 ? OTLM_BF16_FLOOR : OTLM_FP32_FLOOR,
-                       false, bulk_bf16, nts);
+                       false, bulk_bf16, nts, probe);
   if (last < 0) return last;
   bool state64 = false;
   if (refine) {
@@ -657,19 +690,21 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.Dp, ws.Dp64, (size_t)np * kp);
       OTLM_HIP(hipGetLastError());
       const int nts64 = (int)((np + G64_BN - 1) / G64_BN);
-      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, false, nts64);
+      last = run_phase(std::max(last, mm_until_max), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, false, nts64,
+                       false);
       state64 = true;
     } else {
-      last = run_phase(std::max(last, OTLM_MM_WARMUP), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, false, nts);
+      last = run_phase(std::max(last, mm_until_max), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, false, nts,
+                       false);
     }
     if (last < 0) return last;
   }
   if (state64)
     hipLaunchKernelGGL(write_outputs64, dim3((unsigned)B), dim3(256), 0, s, ws.W64, ws.U64, ws.V64, ws.done,
-                       ws.status, ws.iters, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.status, ws.iters, (const int*)ws.fallback, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   else
     hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
-                       ws.iters, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.iters, (const int*)ws.fallback, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   OTLM_HIP(hipGetLastError());
   if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
     std::vector<int> h((size_t)B);
@@ -712,3 +747,4 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
 }  // extern "C"
 
 #include "ragged.hpp"
+#include "mlp.hpp"

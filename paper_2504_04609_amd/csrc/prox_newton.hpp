@@ -41,6 +41,8 @@ struct ProxNewtonArgs {
   const float* DTp;    // [kp, ld_dt] its transpose (coalesced column sweeps)
   const float4* colc;  // per column {1/x_j, ...}
   const int* done;
+  const int* mm_until;  // spectra with it <= mm_until[b] take the MM step instead (null: none)
+  int it;
   int* nit;            // Newton iterations done, accumulated per spectrum
   int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
@@ -135,7 +137,7 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const double* w, cons
 template <class TS, class TW>
 __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<TS, TW> p) {
   const int b = blockIdx.x;
-  if (p.done[b]) return;
+  if (p.done[b] || (p.mm_until && p.it <= p.mm_until[b])) return;
   extern __shared__ double smem[];
   const int n = p.n, k = p.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* a = smem;                    // [n]  D w at the current point

@@ -99,6 +99,8 @@ struct EpiWupd {
   float* W;
   const float4* colc;
   const int* done;
+  const int* mm_until;  // when not null only rows with it <= mm_until[m] take the step
+  int it;
   int ld, k_valid, pen;
   bool do_red;
   __device__ __forceinline__ void elem(int m, int j, float c, float*) const {
@@ -118,7 +120,7 @@ struct EpiWupd {
     } else {  // PEN_L2SQ (shift 0) and PEN_EN share the Lambert-W form
       w = wright_omega<float>(nu - cc.y + cc.w) / cc.z;
     }
-    if (!done[m]) W[o] = w;
+    if (!done[m] && (!mm_until || it <= mm_until[m])) W[o] = w;
   }
   __device__ __forceinline__ void row_partial(int, int, const float*) const {}
 };
@@ -286,7 +288,8 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
                            int np, int kp, int warm, float* __restrict__ V, float* __restrict__ W,
                            float* __restrict__ U, int* __restrict__ done, int* __restrict__ status,
                            int* __restrict__ iters, float* __restrict__ ew_prev, float* __restrict__ ew_best,
-                           int* __restrict__ stall, int* __restrict__ bad) {
+                           int* __restrict__ stall, int* __restrict__ mm_until, int mm_warmup,
+                           int* __restrict__ fallback, int* __restrict__ bad) {
   const int b = blockIdx.x;
   __shared__ double ssum[256];
   double acc = 0.0;
@@ -321,6 +324,56 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
     ew_prev[b] = 0.f;
     ew_best[b] = INFINITY;
     stall[b] = 0;
+    mm_until[b] = warm ? 0 : mm_warmup;
+    fallback[b] = 0;
+  }
+}
+
+// Fallback of a warm start: at the first convergence test, a spectrum whose
+// weight change over the interval exceeds `probe` relative to max|w| (or is
+// not finite) is restarted from the cold start (v = 1, w0_j = sum(y)/(k x_j),
+// u = 0), takes MM steps up to iteration it + mm_warmup, and is flagged.  The
+// caller recomputes a = D w afterwards.  One workgroup per spectrum.
+__global__ void warm_fallback(const float* __restrict__ pwn, const float* __restrict__ pwd, float probe,
+                              const float* __restrict__ Y, const float4* __restrict__ colc, int n, int k, int np,
+                              int kp, int it, int mm_warmup, float* __restrict__ V, unsigned short* __restrict__ Vbf,
+                              float* __restrict__ W, float* __restrict__ Wsnap, float* __restrict__ U,
+                              int* __restrict__ done, int* __restrict__ status, float* __restrict__ ew_prev,
+                              float* __restrict__ ew_best, int* __restrict__ stall, int* __restrict__ mm_until,
+                              int* __restrict__ fallback, int* __restrict__ count) {
+  const int b = blockIdx.x;
+  const float d = pwd[b] > 0.f ? pwn[b] / pwd[b] : 0.f;
+  if (d <= probe) return;  // also skips nothing for NaN: NaN fails the comparison and falls back
+  __shared__ double ssum[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)Y[(size_t)b * n + i];
+  ssum[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double mass = ssum[0];
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const size_t o = (size_t)b * np + i;
+    V[o] = i < n ? 1.f : 0.f;
+    if (Vbf) Vbf[o] = i < n ? (unsigned short)0x3f80 : (unsigned short)0;  // BF16 1.0
+    U[o] = 0.f;
+  }
+  for (int j = threadIdx.x; j < kp; j += blockDim.x) {
+    const float w = j < k ? (float)(mass / k * (double)colc[j].x) : 0.f;
+    W[(size_t)b * kp + j] = w;
+    Wsnap[(size_t)b * kp + j] = w;
+  }
+  if (threadIdx.x == 0) {
+    done[b] = 0;
+    status[b] = 0;
+    ew_prev[b] = 0.f;
+    ew_best[b] = INFINITY;
+    stall[b] = 0;
+    mm_until[b] = it + mm_warmup;
+    fallback[b] = 1;
+    atomicAdd(count, 1);
   }
 }
 
@@ -432,9 +485,10 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
 // Outputs: W (unpadded), log u, log v, iteration counts and status flags.
 __global__ void write_outputs(const float* __restrict__ Wst, const float* __restrict__ U,
                               const float* __restrict__ V, const int* __restrict__ done,
-                              const int* __restrict__ st, const int* __restrict__ it_in, int n, int k, int np,
-                              int kp, int max_iter, float* __restrict__ W, float* __restrict__ logU,
-                              float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
+                              const int* __restrict__ st, const int* __restrict__ it_in,
+                              const int* __restrict__ fallback, int n, int k, int np, int kp, int max_iter,
+                              float* __restrict__ W, float* __restrict__ logU, float* __restrict__ logV,
+                              int* __restrict__ iters, int* __restrict__ status) {
   const int b = blockIdx.x;
   for (int j = threadIdx.x; j < k; j += blockDim.x) W[(size_t)b * k + j] = Wst[(size_t)b * kp + j];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -443,6 +497,6 @@ __global__ void write_outputs(const float* __restrict__ Wst, const float* __rest
   }
   if (threadIdx.x == 0) {
     if (iters) iters[b] = done[b] ? it_in[b] : max_iter;
-    if (status) status[b] = done[b] ? st[b] : 2;
+    if (status) status[b] = (done[b] ? st[b] : 2) | (fallback[b] ? 16 : 0);
   }
 }

@@ -20,12 +20,14 @@ PREC = {"fp32": 0, "bf16": 1}
 REFINE = {"none": 0, "fp32": 1, "fp64": 2}
 WSTEP = {"mm": 0, "exact": 1}
 
-STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED = 1, 2, 4, 8
+STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED, STATUS_FALLBACK = 1, 2, 4, 8, 16
 
 EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info",
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
             "otlm_profile_read", "otlm_ragged_default_opts", "otlm_ragged_create", "otlm_ragged_solve",
-            "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read", "otlm_ragged_free")
+            "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read", "otlm_ragged_free",
+            "otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_get_norm", "otlm_mlp_grad",
+            "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer", "otlm_mlp_free")
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
                    "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
                    "kv_product_bf16", "ktu_product_bf16")
@@ -40,11 +42,16 @@ class OtlmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("lambda_", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double),
-                ("bulk_tol", ctypes.c_double),
+                ("bulk_tol", ctypes.c_double), ("warm_probe", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("fit", ctypes.c_int32),
                 ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32), ("wstep", ctypes.c_int32),
                 ("inner_max", ctypes.c_int32)]
+
+
+class AdamW(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("weight_decay", ctypes.c_double)]
 
 
 class RaggedOpts(ctypes.Structure):
@@ -84,6 +91,21 @@ def load() -> ctypes.CDLL:
     lib.otlm_ragged_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.otlm_ragged_profile_read.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.otlm_ragged_free.argtypes = [vp]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.otlm_mlp_create.argtypes = [i32p, vp, vp, ctypes.POINTER(vp)]
+    lib.otlm_mlp_info.argtypes = [vp, i32p, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.otlm_mlp_set_norm.argtypes = [vp, vp, vp, i64, vp]
+    lib.otlm_mlp_get_norm.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.otlm_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.otlm_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(AdamW), vp, vp]
+    lib.otlm_mlp_get_params.argtypes = [vp, vp, vp]
+    lib.otlm_mlp_set_params.argtypes = [vp, vp, vp]
+    lib.otlm_mlp_infer.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+    lib.otlm_mlp_free.argtypes = [vp]
+    for name in ("otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_get_norm", "otlm_mlp_grad",
+                 "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer",
+                 "otlm_mlp_free"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info", "otlm_solve_batch", "otlm_objective",
                  "otlm_profile_enable", "otlm_profile_read", "otlm_ragged_create", "otlm_ragged_solve",
                  "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read",
@@ -116,6 +138,7 @@ class SolveParams:
     refine_sweeps: int = 200
     bulk_tol: float = 1e-4
     warm: bool = False
+    warm_probe: float = 0.0     # > 0: cold restart of warm starts whose first interval moves w more
     wstep: str = "mm"           # "mm" (one MM step, Algorithm 1) or "exact" (ProxP by Newton)
     inner_max: int = 5
 
@@ -128,6 +151,7 @@ class SolveParams:
         p.fit, p.pen, p.prec = FIT[self.fit], PEN[self.pen], PREC[self.prec]
         p.refine, p.refine_sweeps = REFINE[self.refine], self.refine_sweeps
         p.warm = int(self.warm)
+        p.warm_probe = self.warm_probe
         p.wstep, p.inner_max = WSTEP[self.wstep], self.inner_max
         return p
 
@@ -322,6 +346,98 @@ class RaggedPlan:
     def close(self):
         if getattr(self, "handle", None):
             load().otlm_ragged_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WarmStartMLP:
+    """The warm-start network (otlm_mlp_*): dims = (in, h1, h2, out), initial
+    flat parameters theta (FP32, host NumPy or CUDA tensor)."""
+
+    def __init__(self, dims, theta, stream=None):
+        import numpy as np
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        d = (ctypes.c_int32 * 4)(*self.dims)
+        if isinstance(theta, torch.Tensor):
+            if theta.dtype != torch.float32 or not theta.is_contiguous():
+                raise OtlmError("theta must be a contiguous float32 tensor")
+            tp, self._keep = ctypes.c_void_p(theta.data_ptr()), theta
+        else:
+            self._keep = np.ascontiguousarray(theta, dtype=np.float32)
+            tp = self._keep.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(load().otlm_mlp_create(d, tp, _stream(stream), ctypes.byref(h)), "otlm_mlp_create")
+        self.handle = h
+        self._keep = None
+        self.nparam = self.info()["nparam"]
+
+    def info(self):
+        d = (ctypes.c_int32 * 4)()
+        n, st = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().otlm_mlp_info(self.handle, d, ctypes.byref(n), ctypes.byref(st)), "otlm_mlp_info")
+        return {"dims": tuple(d), "nparam": n.value, "step": st.value}
+
+    def set_norm(self, X, T, stream=None):
+        import torch
+        N = X.shape[0]
+        _need(X, torch.float32, (N, self.dims[0]), "X")
+        _need(T, torch.float32, (N, self.dims[3]), "T")
+        _check(load().otlm_mlp_set_norm(self.handle, _ptr(X), _ptr(T), N, _stream(stream)), "otlm_mlp_set_norm")
+
+    def get_norm(self, stream=None):
+        import torch
+        i_mu = torch.empty(self.dims[0], device="cuda", dtype=torch.float32)
+        i_sd, o_mu, o_sd = torch.empty_like(i_mu), torch.empty(self.dims[3], device="cuda"), None
+        o_sd = torch.empty_like(o_mu)
+        _check(load().otlm_mlp_get_norm(self.handle, _ptr(i_mu), _ptr(i_sd), _ptr(o_mu), _ptr(o_sd),
+                                        _stream(stream)), "otlm_mlp_get_norm")
+        return i_mu, i_sd, o_mu, o_sd
+
+    def grad(self, X, T, idx, stream=None):
+        """(flat gradient, loss) on the minibatch rows idx (CUDA int32)."""
+        import torch
+        g = torch.empty(self.nparam, device=X.device, dtype=torch.float32)
+        loss = torch.empty(1, device=X.device, dtype=torch.float32)
+        _check(load().otlm_mlp_grad(self.handle, _ptr(X), _ptr(T), _ptr(idx), idx.numel(), _ptr(g), _ptr(loss),
+                                    _stream(stream)), "otlm_mlp_grad")
+        return g, loss
+
+    def train_step(self, X, T, idx, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, loss=None,
+                   stream=None):
+        h = AdamW(lr, beta1, beta2, eps, weight_decay)
+        _check(load().otlm_mlp_train_step(self.handle, _ptr(X), _ptr(T), _ptr(idx), idx.numel(), ctypes.byref(h),
+                                          _ptr(loss), _stream(stream)), "otlm_mlp_train_step")
+
+    def params(self, stream=None):
+        import torch
+        t = torch.empty(self.nparam, device="cuda", dtype=torch.float32)
+        _check(load().otlm_mlp_get_params(self.handle, _ptr(t), _stream(stream)), "otlm_mlp_get_params")
+        return t
+
+    def set_params(self, theta, stream=None):
+        _check(load().otlm_mlp_set_params(self.handle, _ptr(theta), _stream(stream)), "otlm_mlp_set_params")
+
+    def infer(self, Y, n_u, n_v, prec="bf16", logU=None, logV=None, W=None, stream=None):
+        """Split prediction (logU or None, logV [B, n_v], W [B, out - n_u - n_v])."""
+        import torch
+        B = Y.shape[0]
+        _need(Y, torch.float32, (B, self.dims[0]), "Y")
+        k = self.dims[3] - n_u - n_v
+        logV = torch.empty((B, n_v), device=Y.device, dtype=torch.float32) if logV is None else logV
+        W = torch.empty((B, k), device=Y.device, dtype=torch.float32) if W is None else W
+        _check(load().otlm_mlp_infer(self.handle, _ptr(Y), B, PREC[prec], n_u, n_v, _ptr(logU), _ptr(logV), _ptr(W),
+                                     _stream(stream)), "otlm_mlp_infer")
+        return logU, logV, W
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().otlm_mlp_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -203,3 +203,17 @@ class RaggedWorkload:
 
 
 CONFIG4 = RaggedWorkload()
+
+
+# ---------------------------------------------------------------- warm-start network
+def mlp_init(dims, seed: int) -> np.ndarray:
+    """Initial flat parameters [W1, b1, W2, b2, W3, b3] of the warm-start network
+    (W_l [out, in] row-major): every entry of layer l drawn U(-1/sqrt(in_l),
+    1/sqrt(in_l)) from PCG64(SeedSequence([seed, l])), FP32."""
+    parts = []
+    for layer, (a, b) in enumerate(zip(dims[:-1], dims[1:])):
+        rng = rng_for(seed, layer)
+        bound = 1.0 / np.sqrt(a)
+        parts.append(rng.uniform(-bound, bound, b * a))
+        parts.append(rng.uniform(-bound, bound, b))
+    return np.concatenate(parts).astype(np.float32)

@@ -36,8 +36,8 @@ def test_library_exports_every_declared_symbol():
 
 @needs_lib
 def test_params_struct_matches_header():
-    # 7 doubles + 10 int32 in include/otlm.h
-    assert ctypes.sizeof(otlm.Params) == 7 * 8 + 10 * 4
+    # 8 doubles + 10 int32 in include/otlm.h
+    assert ctypes.sizeof(otlm.Params) == 8 * 8 + 10 * 4
     p = otlm.Params()
     otlm.load().otlm_default_params(ctypes.byref(p))
     assert p.fit == otlm.FIT["kl"] and p.pen == otlm.PEN["none"] and p.max_iter == 1000
