@@ -310,8 +310,8 @@ int otlm_ragged_free(otlm_ragged r);
  * [W1, b1, W2, b2, W3, b3]) that maps a target spectrum y to a starting point
  * of Algorithm 1, the (log u, log v, w) the solver reaches for it.  Inputs are
  * standardised per feature and targets per output (after clamping to
- * [-50, 50]) with statistics of the training set; the loss is the mean squared
- * error of the standardised outputs.  Trained by AdamW on minibatches of a
+ * [-50, 50]) with statistics of the training set; the loss is the (weighted)
+ * mean squared error of the standardised outputs.  Trained by AdamW on minibatches of a
  * training set held in device memory; FP32 training, FP32 or BF16 inference.
  * ------------------------------------------------------------------------- */
 typedef struct otlm_mlp_s* otlm_mlp;
@@ -337,6 +337,12 @@ int otlm_mlp_info(otlm_mlp m, int32_t* dims, int64_t* nparam, int64_t* step);
  * per column mean and standard deviation (floored at 1e-6), FP64 sums.
  * Synchronises `stream`. */
 int otlm_mlp_set_norm(otlm_mlp m, const float* X, const float* T, int64_t N, void* stream);
+
+/* Loss weight omega_o >= 0 of every output (host or device FP32 [out]; the
+ * default is 1): the loss is 1/(B out) sum_b sum_o omega_o (z_bo - t_bo)^2.
+ * Synchronises `stream`.  Errors: OTLM_E_INVALID for a negative or non-finite
+ * weight. */
+int otlm_mlp_set_loss_weights(otlm_mlp m, const float* weights, void* stream);
 
 /* Copy the standardisation statistics out (any pointer may be NULL). */
 int otlm_mlp_get_norm(otlm_mlp m, float* in_mu, float* in_sd, float* out_mu, float* out_sd, void* stream);

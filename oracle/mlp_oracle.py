@@ -12,9 +12,9 @@ definition, in float64 NumPy:
 * multilayer perceptron  x -> GELU(x W1^T + b1) -> GELU(. W2^T + b2) -> . W3^T + b3
   with weights W_l stored [out_l, in_l] row-major and the exact (erf) GELU,
   gelu(z) = z Phi(z), Phi the standard normal CDF;
-* mean squared error over every output of a minibatch,
-  L = 1 / (B O) sum_b sum_o (z_bo - t_bo)^2, and its gradient by the chain
-  rule (backpropagation);
+* weighted mean squared error over every output of a minibatch,
+  L = 1 / (B O) sum_b sum_o omega_o (z_bo - t_bo)^2 (omega = 1 unless given),
+  and its gradient by the chain rule (backpropagation);
 * AdamW (Loshchilov & Hutter, "Decoupled Weight Decay Regularization"):
   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
   p <- p - lr (m / (1 - b1^t) / (sqrt(v / (1 - b2^t)) + eps) + wd p),
@@ -78,15 +78,17 @@ def forward(theta, dims, X):
     return Z3, (X, Z1, H1, Z2, H2)
 
 
-def loss_and_grad(theta, dims, X, T):
-    """Mean squared error over all outputs and its gradient (flat, as theta)."""
+def loss_and_grad(theta, dims, X, T, weights=None):
+    """(Weighted) mean squared error over all outputs and its gradient (flat,
+    as theta)."""
     W1, b1, W2, b2, W3, b3 = unpack(theta, dims)
     Z3, (X, Z1, H1, Z2, H2) = forward(theta, dims, X)
     T = np.asarray(T, dtype=np.float64)
     B, O = Z3.shape
+    om = np.ones(O) if weights is None else np.asarray(weights, dtype=np.float64)
     R = Z3 - T
-    L = float(np.sum(R * R) / (B * O))
-    dZ3 = 2.0 * R / (B * O)
+    L = float(np.sum(om * R * R) / (B * O))
+    dZ3 = 2.0 * om * R / (B * O)
     dW3 = dZ3.T @ H2
     db3 = dZ3.sum(axis=0)
     dZ2 = (dZ3 @ W3) * gelu_prime(Z2)

@@ -17,6 +17,7 @@ struct otlm_mlp_s {
   unsigned short* wbf = nullptr;  // BF16 W1 | W2 | W3
   bool bf_valid = false;
   float *in_mu = nullptr, *in_sd = nullptr, *out_mu = nullptr, *out_sd = nullptr;
+  float* out_w = nullptr;  // loss weight of every output
   int64_t step = 0;
   // activation workspace for `cap` rows
   int64_t cap = 0;
@@ -94,7 +95,7 @@ int mlp_forward_backward(otlm_mlp_s* m, const float* Xraw, const float* T, const
   mlp_gemm<false, false>(GemmArgs{m->H1, h1, W2, h1, B, h2, h1}, EpiBiasGelu{b2, m->Z2, m->H2, nullptr, h2, false},
                          s);
   mlp_gemm<false, false>(GemmArgs{m->H2, h2, W3, h2, B, out, h2},
-                         EpiLossOut{b3, T, idx, out, m->out_mu, m->out_sd, m->dZ3, out,
+                         EpiLossOut{b3, T, idx, out, m->out_mu, m->out_sd, m->out_w, m->dZ3, out,
                                     (float)(2.0 / ((double)B * out)), m->part, ntiles, true},
                          s);
   // backward
@@ -153,7 +154,8 @@ int otlm_mlp_create(const int32_t* dims, const float* theta, void* stream, otlm_
   auto& L = m->allocs;
   if (!(mlp_alloc(L, &m->theta, o) && mlp_alloc(L, &m->grad, o) && mlp_alloc(L, &m->m, o) &&
         mlp_alloc(L, &m->v, o) && mlp_alloc(L, &m->wbf, nw) && mlp_alloc(L, &m->in_mu, dims[0]) &&
-        mlp_alloc(L, &m->in_sd, dims[0]) && mlp_alloc(L, &m->out_mu, dims[3]) && mlp_alloc(L, &m->out_sd, dims[3])))
+        mlp_alloc(L, &m->in_sd, dims[0]) && mlp_alloc(L, &m->out_mu, dims[3]) && mlp_alloc(L, &m->out_sd, dims[3]) &&
+        mlp_alloc(L, &m->out_w, dims[3])))
     return fail(OTLM_E_NOMEM);
   std::vector<float> zeros(std::max(dims[0], dims[3]), 0.f), ones(std::max(dims[0], dims[3]), 1.f);
   if (hipMemcpyAsync(m->theta, theta, (size_t)o * sizeof(float), hipMemcpyDefault, s) != hipSuccess ||
@@ -164,6 +166,7 @@ int otlm_mlp_create(const int32_t* dims, const float* theta, void* stream, otlm_
       hipMemcpyAsync(m->in_sd, ones.data(), dims[0] * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(m->out_mu, zeros.data(), dims[3] * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(m->out_sd, ones.data(), dims[3] * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(m->out_w, ones.data(), dims[3] * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(OTLM_E_HIP);
   *out = m;
@@ -203,6 +206,19 @@ int otlm_mlp_set_norm(otlm_mlp m, const float* X, const float* T, int64_t N, voi
   (void)hipFree(s1);
   (void)hipFree(s2);
   return (e1 == hipSuccess && e2 == hipSuccess) ? OTLM_OK : OTLM_E_HIP;
+}
+
+int otlm_mlp_set_loss_weights(otlm_mlp m, const float* weights, void* stream) {
+  if (!m || !weights) return OTLM_E_INVALID;
+  std::vector<float> h((size_t)m->dims[3]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  OTLM_HIP(hipMemcpyAsync(h.data(), weights, h.size() * sizeof(float), hipMemcpyDefault, s));
+  OTLM_HIP(hipStreamSynchronize(s));
+  for (float w : h)
+    if (!(w >= 0.f) || !std::isfinite(w)) return OTLM_E_INVALID;
+  OTLM_HIP(hipMemcpyAsync(m->out_w, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  OTLM_HIP(hipStreamSynchronize(s));
+  return OTLM_OK;
 }
 
 int otlm_mlp_get_norm(otlm_mlp m, float* in_mu, float* in_sd, float* out_mu, float* out_sd, void* stream) {

@@ -8,8 +8,8 @@
 // forward  Z_l = H_{l-1} W_l^T (+ b_l, GELU)                 (A, Bt k-contiguous)
 // backward dH_{l-1} = dZ_l W_l   (then x GELU'(Z_{l-1}))      (B stored [Kd, N])
 //          dW_l = dZ_l^T H_{l-1}                               (A and B stored [Kd, .])
-// GELU is the exact form z Phi(z) (erf).  The loss is the mean squared error
-// over all outputs of standardised targets, clamp(t, +-T_CLAMP) - mu) / sd.
+// GELU is the exact form z Phi(z) (erf).  The loss is the weighted mean squared
+// error over all outputs of standardised targets, (clamp(t, +-T_CLAMP) - mu) / sd.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "solver_kernels.hpp"
@@ -45,8 +45,9 @@ struct EpiBiasGelu {
 };
 
 // output layer in training: z = c + b_n, residual r = z - t^ with the
-// standardised target t^ of row idx[m] (idx null: row m); stores the loss
-// gradient dZ = scale r (scale = 2 / (B O)) and the per-tile sum of r^2
+// standardised target t^ of row idx[m] (idx null: row m); with the output
+// weight om_n it stores the loss gradient dZ = scale om_n r (scale = 2 / (B O))
+// and the per-tile sum of om_n r^2
 struct EpiLossOut {
   static constexpr int NRED = 1;
   static constexpr bool RED_IS_MAX[2] = {false, false};
@@ -56,6 +57,7 @@ struct EpiLossOut {
   int ldt;
   const float* mu;
   const float* sd;
+  const float* om;
   float* dZ;
   int ld;
   float scale;
@@ -66,8 +68,9 @@ struct EpiLossOut {
     const int row = idx ? idx[m] : m;
     const float t = fminf(fmaxf(T[(size_t)row * ldt + n], -MLP_T_CLAMP), MLP_T_CLAMP);
     const float r = (c + bias[n]) - (t - mu[n]) / sd[n];
-    dZ[(size_t)m * ld + n] = scale * r;
-    red[0] += r * r;
+    const float w = om[n];
+    dZ[(size_t)m * ld + n] = scale * w * r;
+    red[0] += w * r * r;
   }
   __device__ __forceinline__ void row_partial(int m, int tile, const float* v) const {
     part[(size_t)m * ntiles + tile] = v[0];

@@ -57,6 +57,7 @@ struct Workspace {
   int* nit = nullptr;
   int* mm_until = nullptr;  // last iteration of each spectrum's MM warm-up (exact weight prox)
   int* fallback = nullptr;  // 1 when a warm start was replaced by the cold start
+  int* it_base = nullptr;   // per-spectrum offset of refinement-phase iteration indices
   unsigned short *Vbf = nullptr, *Ubf = nullptr;
   // FP64 refinement state
   int64_t B64 = 0;
@@ -81,7 +82,7 @@ struct Workspace {
     ew_best = nullptr;
     stall = nullptr;
     nit = nullptr;
-    mm_until = fallback = nullptr;
+    mm_until = fallback = it_base = nullptr;
     Vbf = Ubf = nullptr;
   }
   void release64() {
@@ -185,6 +186,7 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.nit, (size_t)B);
   rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
   rc |= dev_alloc(ws, &ws.fallback, (size_t)B);
+  rc |= dev_alloc(ws, &ws.it_base, (size_t)B);
   rc |= dev_alloc(ws, &ws.Vbf, bn);
   rc |= dev_alloc(ws, &ws.Ubf, bn);
   if (rc != OTLM_OK) {
@@ -474,6 +476,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
 
   OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
   if (exact) OTLM_HIP(hipMemsetAsync(ws.nit, 0, (size_t)B * sizeof(int), s));
+  OTLM_HIP(hipMemsetAsync(ws.it_base, 0, (size_t)B * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
                      p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
@@ -640,7 +643,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
           weight_change(use64, 0);
           hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, ws.psn, ws.psd, nts_phase, ws.pwn, ws.pwd,
                              M, (float)tol, floor_w, it, ws.ew_prev, ws.ew_best, ws.stall, ws.done, ws.iters,
-                             ws.status, ws.flags, nullptr);
+                             ws.status, ws.flags, nullptr, (const int*)ws.it_base);
         }
         const bool fb = probe && first_check;
         if (fb)
@@ -679,8 +682,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   if (last < 0) return last;
   bool state64 = false;
   if (refine) {
-    hipLaunchKernelGGL(reopen_spectra, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, M, ws.done, ws.status,
-                       ws.ew_prev, ws.ew_best, ws.stall);
+    hipLaunchKernelGGL(reopen_spectra, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, M, last, ws.done,
+                       ws.status, (const int*)ws.iters, ws.it_base, ws.ew_prev, ws.ew_best, ws.stall);
     if (fp64) {
       const size_t bn = (size_t)B * np;
       hipLaunchKernelGGL(convert_f32_to_f64, dim3(1024), dim3(256), 0, s, ws.V, ws.V64, bn);
@@ -701,10 +704,10 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
   if (state64)
     hipLaunchKernelGGL(write_outputs64, dim3((unsigned)B), dim3(256), 0, s, ws.W64, ws.U64, ws.V64, ws.done,
-                       ws.status, ws.iters, (const int*)ws.fallback, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.status, ws.iters, (const int*)ws.fallback, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   else
     hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
-                       ws.iters, (const int*)ws.fallback, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.iters, (const int*)ws.fallback, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   OTLM_HIP(hipGetLastError());
   if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
     std::vector<int> h((size_t)B);

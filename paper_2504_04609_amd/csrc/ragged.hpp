@@ -226,7 +226,7 @@ void rg_chunk(otlm_ragged_s* r, int c, hipStream_t s) {
                        r->Wst, r->Wsnap, 0, r->pwn, r->pwd);
     hipLaunchKernelGGL(check_convergence, dim3(1), dim3(1024), 0, s, r->psn, r->psd, r->ts, r->pwn, r->pwd,
                        (int)r->B, (float)r->p.tol, OTLM_FP32_FLOOR, 0, r->ew_prev, r->ew_best, r->stall, r->done,
-                       r->iters, r->status, r->flags, r->it_dev);
+                       r->iters, r->status, r->flags, r->it_dev, (const int*)nullptr);
     rg_compact_rows(r, r->tile, s);
   }
 }

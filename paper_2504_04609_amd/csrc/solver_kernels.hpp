@@ -423,14 +423,15 @@ __global__ __launch_bounds__(256) void interval_change(const T* __restrict__ W, 
 // tests has reached the noise floor of its precision on an ill-conditioned
 // problem: it stops with status 8.  One workgroup; also counts the spectra
 // still active into *active.  The iteration index recorded for a stopping
-// spectrum is `it`, or *it_dev when it_dev is not null.
+// spectrum is `it` (or *it_dev when it_dev is not null) plus it_base[b] when
+// it_base is not null.
 constexpr int OTLM_STALL_CHECKS = 6;
 __global__ void check_convergence(const float* __restrict__ psn, const float* __restrict__ psd, int nts,
                                   const float* __restrict__ pwn, const float* __restrict__ pwd, int B, float tol,
                                   float floor_w, int it, float* __restrict__ ew_prev, float* __restrict__ ew_best,
                                   int* __restrict__ stall, int* __restrict__ done, int* __restrict__ iters,
                                   int* __restrict__ status, int* __restrict__ active,
-                                  const int* __restrict__ it_dev) {
+                                  const int* __restrict__ it_dev, const int* __restrict__ it_base) {
   __shared__ int cnt[1024];
   if (it_dev) it = it_dev[0];  // iteration index kept on the device (captured chunks)
   int count = 0;
@@ -467,7 +468,7 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
       if (st) {
         done[b] = 1;
         status[b] = st;
-        iters[b] = it;
+        iters[b] = it + (it_base ? it_base[b] : 0);
       } else {
         ++count;
       }
@@ -486,9 +487,9 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
 __global__ void write_outputs(const float* __restrict__ Wst, const float* __restrict__ U,
                               const float* __restrict__ V, const int* __restrict__ done,
                               const int* __restrict__ st, const int* __restrict__ it_in,
-                              const int* __restrict__ fallback, int n, int k, int np, int kp, int max_iter,
-                              float* __restrict__ W, float* __restrict__ logU, float* __restrict__ logV,
-                              int* __restrict__ iters, int* __restrict__ status) {
+                              const int* __restrict__ fallback, const int* __restrict__ it_base, int n, int k,
+                              int np, int kp, int max_iter, float* __restrict__ W, float* __restrict__ logU,
+                              float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
   const int b = blockIdx.x;
   for (int j = threadIdx.x; j < k; j += blockDim.x) W[(size_t)b * k + j] = Wst[(size_t)b * kp + j];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -496,7 +497,7 @@ __global__ void write_outputs(const float* __restrict__ Wst, const float* __rest
     logV[(size_t)b * n + i] = logf(V[(size_t)b * np + i]);
   }
   if (threadIdx.x == 0) {
-    if (iters) iters[b] = done[b] ? it_in[b] : max_iter;
+    if (iters) iters[b] = done[b] ? it_in[b] : max_iter + it_base[b];
     if (status) status[b] = (done[b] ? st[b] : 2) | (fallback[b] ? 16 : 0);
   }
 }

@@ -128,8 +128,8 @@ __global__ void convert_f32_to_f64(const float* __restrict__ x, double* __restri
 __global__ void write_outputs64(const double* __restrict__ Wst, const double* __restrict__ U,
                                 const double* __restrict__ V, const int* __restrict__ done,
                                 const int* __restrict__ st, const int* __restrict__ it_in,
-                                const int* __restrict__ fallback, int n, int k, int np,
-                                int kp, int last_iter, float* __restrict__ W, float* __restrict__ logU,
+                                const int* __restrict__ fallback, const int* __restrict__ it_base, int n, int k,
+                                int np, int kp, int last_iter, float* __restrict__ W, float* __restrict__ logU,
                                 float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
   const int b = blockIdx.x;
   for (int j = threadIdx.x; j < k; j += blockDim.x) W[(size_t)b * k + j] = (float)Wst[(size_t)b * kp + j];
@@ -138,17 +138,23 @@ __global__ void write_outputs64(const double* __restrict__ Wst, const double* __
     logV[(size_t)b * n + i] = (float)log(V[(size_t)b * np + i]);
   }
   if (threadIdx.x == 0) {
-    if (iters) iters[b] = done[b] ? it_in[b] : last_iter;
+    if (iters) iters[b] = done[b] ? it_in[b] : last_iter + it_base[b];
     if (status) status[b] = (done[b] ? st[b] : 2) | (fallback[b] ? 16 : 0);
   }
 }
 
 // Start of a refinement phase: every spectrum that has not failed becomes
 // active again (its bulk-phase test used a looser tolerance).
-__global__ void reopen_spectra(int B, int* __restrict__ done, int* __restrict__ status, float* __restrict__ ew_prev,
+// it_base[b] becomes the spectrum's own bulk iteration count minus `last` (the
+// iteration at which the bulk phase ended for the batch), so that iteration
+// indices of the refinement phase plus it_base count the spectrum's own
+// iterations.
+__global__ void reopen_spectra(int B, int last, int* __restrict__ done, int* __restrict__ status,
+                               const int* __restrict__ iters, int* __restrict__ it_base, float* __restrict__ ew_prev,
                                float* __restrict__ ew_best, int* __restrict__ stall) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
+  it_base[b] = (done[b] ? iters[b] : last) - last;
   if (status[b] != 4) {
     done[b] = 0;
     status[b] = 0;

@@ -26,7 +26,7 @@ EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
             "otlm_profile_read", "otlm_ragged_default_opts", "otlm_ragged_create", "otlm_ragged_solve",
             "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read", "otlm_ragged_free",
-            "otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_get_norm", "otlm_mlp_grad",
+            "otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_set_loss_weights", "otlm_mlp_get_norm", "otlm_mlp_grad",
             "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer", "otlm_mlp_free")
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
                    "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
@@ -96,13 +96,15 @@ def load() -> ctypes.CDLL:
     lib.otlm_mlp_info.argtypes = [vp, i32p, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.otlm_mlp_set_norm.argtypes = [vp, vp, vp, i64, vp]
     lib.otlm_mlp_get_norm.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.otlm_mlp_set_loss_weights.argtypes = [vp, vp, vp]
     lib.otlm_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     lib.otlm_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(AdamW), vp, vp]
     lib.otlm_mlp_get_params.argtypes = [vp, vp, vp]
     lib.otlm_mlp_set_params.argtypes = [vp, vp, vp]
     lib.otlm_mlp_infer.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
     lib.otlm_mlp_free.argtypes = [vp]
-    for name in ("otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_get_norm", "otlm_mlp_grad",
+    for name in ("otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_set_loss_weights",
+                 "otlm_mlp_get_norm", "otlm_mlp_grad",
                  "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer",
                  "otlm_mlp_free"):
         getattr(lib, name).restype = ctypes.c_int
@@ -389,6 +391,14 @@ class WarmStartMLP:
         _need(X, torch.float32, (N, self.dims[0]), "X")
         _need(T, torch.float32, (N, self.dims[3]), "T")
         _check(load().otlm_mlp_set_norm(self.handle, _ptr(X), _ptr(T), N, _stream(stream)), "otlm_mlp_set_norm")
+
+    def set_loss_weights(self, weights, stream=None):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.shape != (self.dims[3],):
+            raise OtlmError(f"weights must have shape ({self.dims[3]},)")
+        _check(load().otlm_mlp_set_loss_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "otlm_mlp_set_loss_weights")
 
     def get_norm(self, stream=None):
         import torch

@@ -113,6 +113,40 @@ class Workload:
         idx = range(self.B) if idx is None else idx
         return np.stack([make_target(dic, self.seed, int(b), self.shift, self.gain)[0] for b in idx])
 
+    def targets_fast(self, idx=None, dic: Dictionary | None = None, device: str = "cpu", chunk: int = 2048):
+        """The same targets as targets(), as a torch FP32 tensor on `device`: the
+        per-spectrum random draws are taken exactly as make_target takes them
+        and the shifted peaks are evaluated in FP64 with torch in chunks."""
+        import torch
+        dic = dic or self.dictionary()
+        idx = list(range(self.B)) if idx is None else [int(b) for b in idx]
+        k, n = dic.centres.size, dic.x.size
+        x = torch.as_tensor(dic.x, dtype=torch.float64, device=device)
+        c = torch.as_tensor(dic.centres, dtype=torch.float64, device=device)
+        sg = torch.as_tensor(dic.sigmas, dtype=torch.float64, device=device)
+        out = torch.empty((len(idx), n), dtype=torch.float32, device=device)
+        for s0 in range(0, len(idx), chunk):
+            part = idx[s0:s0 + chunk]
+            w = np.empty((len(part), k))
+            dg = np.empty((len(part), 2))
+            eta = np.empty((len(part), n))
+            for r, b in enumerate(part):
+                rng = rng_for(self.seed, b)
+                w[r] = rng.exponential(1.0, k)
+                dg[r, 0] = rng.uniform(-self.shift, self.shift) if self.shift > 0 else 0.0
+                dg[r, 1] = rng.uniform(self.gain[0], self.gain[1]) if self.gain[1] > self.gain[0] else self.gain[0]
+                eta[r] = np.abs(rng.normal(0.0, 1e-3, n))
+            wt = torch.as_tensor(w, device=device)
+            delta = torch.as_tensor(dg[:, 0], device=device)
+            gain = torch.as_tensor(dg[:, 1], device=device)
+            d = x[None, :, None] - (c[None, None, :] + delta[:, None, None])      # [b, n, k]
+            g = torch.exp(-0.5 * (d / sg[None, None, :]) ** 2)
+            g = torch.where(d.abs() > 5.0 * sg[None, None, :], torch.zeros_like(g), g)
+            g = g / g.sum(dim=1, keepdim=True)
+            y = gain[:, None] * torch.einsum("bnk,bk->bn", g, wt) + torch.as_tensor(eta, device=device)
+            out[s0:s0 + len(part)] = y.to(torch.float32)
+        return out
+
     def cost(self) -> np.ndarray:
         x = grid(self.n)
         return sq_cost(x, x)

@@ -69,12 +69,16 @@ def test_standardisation_matches_oracle():
     np.testing.assert_allclose(o_sd, sd, rtol=1e-6)
 
 
-@pytest.mark.parametrize("B", [16, 48])
-def test_gradient_matches_oracle(B):
+@pytest.mark.parametrize("B,weighted", [(16, False), (48, False), (32, True)])
+def test_gradient_matches_oracle(B, weighted):
     theta = synth.mlp_init(DIMS, 5)
     net = otlm.WarmStartMLP(DIMS, theta)
     X, T = data(200, DIMS, 6)
     net.set_norm(gpu(X), gpu(T))
+    om = None
+    if weighted:
+        om = np.concatenate([np.zeros(16), np.ones(16), np.full(16, 4.0)]).astype(np.float32)
+        net.set_loss_weights(om)
     idx = np.random.default_rng(7).choice(200, B, replace=False).astype(np.int32)
     g, loss = net.grad(gpu(X), gpu(T), gpu(idx, torch.int32))
     torch.cuda.synchronize()
@@ -82,7 +86,7 @@ def test_gradient_matches_oracle(B):
     o_mu, o_sd = omlp.column_stats(T, clamp=omlp.T_CLAMP)
     Xh = omlp.standardise(X[idx], i_mu, i_sd)
     Th = omlp.standardise(T[idx], o_mu, o_sd, clamp=omlp.T_CLAMP)
-    L, gref = omlp.loss_and_grad(theta.astype(np.float64), DIMS, Xh, Th)
+    L, gref = omlp.loss_and_grad(theta.astype(np.float64), DIMS, Xh, Th, weights=om)
     assert float(loss.cpu()) == pytest.approx(L, rel=1e-5)
     for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), blocks(g.cpu().numpy(), DIMS), blocks(gref, DIMS)):
         assert rel(a, b) <= 1e-4, name

@@ -65,6 +65,17 @@ def test_gradient_matches_central_differences():
     Z, _ = mlp.forward(theta, DIMS, X)
     assert L == pytest.approx(np.mean((Z - T) ** 2), rel=1e-14)
     assert mlp.loss_and_grad(theta, DIMS, X, Z + 0.25)[0] == pytest.approx(0.0625, rel=1e-12)
+    # output weights scale each output's share of the loss; the weighted
+    # gradient is the weighted sum of single-output gradients
+    om = np.array([0.0, 2.0, 1.0, 0.5, 3.0, 1.0])
+    Lw, gw = mlp.loss_and_grad(theta, DIMS, X, T, weights=om)
+    assert Lw == pytest.approx(np.mean(om * (Z - T) ** 2), rel=1e-14)
+    parts = []
+    for o in range(DIMS[-1]):
+        e = np.zeros(DIMS[-1])
+        e[o] = 1.0
+        parts.append(om[o] * mlp.loss_and_grad(theta, DIMS, X, T, weights=e)[1])
+    np.testing.assert_allclose(gw, np.sum(parts, axis=0), rtol=1e-10, atol=1e-14)
 
 
 def test_adamw_closed_forms():

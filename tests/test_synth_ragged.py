@@ -43,3 +43,13 @@ def test_pack_layout():
     # a subset keeps the per-spectrum draws
     ko2, ns2, kd2, D2, Y2 = wl.pack([5, 2])
     assert list(kd2) == [kd[5], kd[2]]
+
+
+def test_fast_targets_equal_the_reference_generator():
+    import torch
+    wl = synth.CONFIG5_TRAIN
+    dic = wl.dictionary()
+    idx = [0, 7, 199_999]
+    ref = wl.targets(idx, dic=dic).astype(np.float32)
+    fast = wl.targets_fast(idx, dic=dic, chunk=2).numpy()
+    np.testing.assert_allclose(fast, ref, rtol=1e-6, atol=1e-9)
