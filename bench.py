@@ -2,29 +2,41 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--sample S]
 
-Workload (batched plain-method workload): 4096 synthetic spectra, n = 1024 bins,
-k = 64 Gaussian peaks, squared-distance cost, eps = 0.005, KL datafit
-(lambda = 1), l1 penalty 1e-2.  Inputs are resident in HBM and K is prebuilt
-before the timed region; one step is one otlm_solve_batch call over the batch.
+Headline workload (held-out targets of the learned-warm-start workload): 4096
+synthetic spectra, n = 1024 bins, k = 64 Gaussian peaks (the batched
+workload's generator and dictionary), squared-distance cost, eps = 0.002, KL
+datafit (lambda = 1), l1 penalty 1e-2.  Inputs are resident in HBM and K is
+prebuilt before the timed region; one step is one solve of the whole batch
+through the C-ABI (for the warm arms: the network's BF16 inference plus the
+solve, including any fallback restarts).
+
+Before the timed region the warm-start network (1024 -> 512 -> 512 -> 2112,
+GELU) is trained on the GPU with the library's kernels on 200 000 targets of
+the same generator (other seeds), solved by the library itself; generation,
+solve and training times are reported apart.
 
 A spectrum counts as solved when its weights are within 1e-5 (relative l2) of
-the FP64 oracle's fixed point.  The oracle solves S sampled spectra (seed 3) to
-tol 1e-10; the solved fraction of the sample scales the batch.  That oracle run
-is also the CPU baseline (timed on the host cores it used).
+the FP64 oracle's fixed point.  The oracle solves S sampled spectra (seed 3)
+to tol 1e-10; the solved fraction of the sample scales the batch.  That oracle
+run is also the CPU baseline (timed on the host cores it used).
 
-Arms (all cold start, all through the C-ABI):
-  paper_mm       Algorithm 1 as printed: one MM weight step per iteration, FP32,
-                 300 iterations (it does not converge on this l1 workload)
-  exact_fp32     weight prox solved exactly per iteration (Newton), FP32 state
-  exact_fp32_64  the same with an FP64 refinement phase (headline)
-  exact_bf16_64  BF16 kernel products in the bulk phase, then the FP64 refinement
+Arms (through the C-ABI):
+  paper_mm          Algorithm 1 as printed: one MM weight step per iteration,
+                    FP32, cold, 300 iterations (it does not converge here)
+  fp32_cold         weight prox solved exactly per iteration (Newton), FP32, cold
+  fp32_64_cold      the same with an FP64 refinement phase (cold baseline)
+  bf16_64_cold      BF16 kernel products in the bulk phase, FP64 refinement, cold
+  bf16warm_fp32_64  BF16 network inference -> warm start (probe 0.5) -> FP32
+                    bulk -> FP64 refinement  (headline)
+  bf16warm_bf16_64  the same with BF16 bulk kernel products
 
-Secondary row "ragged" (skip with --no-ragged): 8192 spectra with their own
-grid length n in {256, 512, 1024, 2048} and dictionary (k in {16..128}
-Gaussian peaks), L2 + TV datafit (1.0, 0.1), ridge 1e-3, eps 0.005, FP32,
-solved by one otlm_ragged plan (grouped kernel products, banded dictionary
-steps with 4 MM steps per iteration, graph-replayed check intervals), checked
-against the oracle on one spectrum per (n, k) cell.
+Secondary rows: "batched" (the batched workload, eps = 0.005, cold FP32 +
+FP64) and "ragged" (skip with --no-ragged): 8192 spectra with their own grid
+length n in {256, 512, 1024, 2048} and dictionary (k in {16..128} Gaussian
+peaks), L2 + TV datafit (1.0, 0.1), ridge 1e-3, eps 0.005, FP32, solved by one
+otlm_ragged plan (grouped kernel products, banded dictionary steps with 4 MM
+steps per iteration, graph-replayed check intervals), checked against the
+oracle on one spectrum per (n, k) cell.
 
 Prints one JSON line; the roofline entry is the kernel class with the largest
 total time in the headline arm, timed with HIP events on the solve's stream
@@ -45,6 +57,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6, "bf16_mfma": 2500.0}  # TFLOP/s, MI355X
+HEADLINE = "bf16warm_fp32_64"
+BASELINE_ARM = "fp32_64_cold"
+PROBE = 0.5
 
 
 def kernel_nonzero_fraction(C, eps):
@@ -53,18 +68,31 @@ def kernel_nonzero_fraction(C, eps):
     return float(np.mean(K32 >= np.finfo(np.float32).tiny))
 
 
+def cores_used():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def arm_params(name, wl, otlm):
     base = dict(eps=wl.eps, fit=wl.fit, pen=wl.pen, lam=wl.lam, alpha=wl.alpha, check_every=5)
+    exact = dict(base, max_iter=400, wstep="exact", inner_max=5)
     if name == "paper_mm":
         return otlm.SolveParams(**base, tol=0.0, max_iter=300, wstep="mm")
-    if name == "exact_fp32":
-        return otlm.SolveParams(**base, tol=1e-6, max_iter=400, wstep="exact", inner_max=5)
-    if name == "exact_fp32_64":
-        return otlm.SolveParams(**base, tol=1e-9, bulk_tol=1e-4, max_iter=400, wstep="exact", inner_max=5,
-                                refine="fp64", refine_sweeps=200)
-    if name == "exact_bf16_64":
-        return otlm.SolveParams(**base, tol=1e-9, bulk_tol=1e-3, max_iter=400, wstep="exact", inner_max=5,
-                                prec="bf16", refine="fp64", refine_sweeps=300)
+    if name == "fp32_cold":
+        return otlm.SolveParams(**exact, tol=1e-6)
+    if name == "fp32_64_cold":
+        return otlm.SolveParams(**exact, tol=1e-9, bulk_tol=1e-4, refine="fp64", refine_sweeps=300)
+    if name == "bf16_64_cold":
+        return otlm.SolveParams(**exact, tol=1e-9, bulk_tol=1e-3, prec="bf16", refine="fp64", refine_sweeps=300)
+    if name == "bf16warm_fp32_64":
+        return otlm.SolveParams(**exact, tol=1e-9, bulk_tol=1e-4, refine="fp64", refine_sweeps=300, warm=True,
+                                warm_probe=PROBE)
+    if name == "bf16warm_bf16_64":
+        return otlm.SolveParams(**exact, tol=1e-9, bulk_tol=1e-3, prec="bf16", refine="fp64", refine_sweeps=300,
+                                warm=True, warm_probe=PROBE)
     raise ValueError(name)
 
 
@@ -80,12 +108,15 @@ def roofline(prof, B, n, k, phi):
         peak = {"f64": PEAK["fp64_mfma"], "bf16": PEAK["bf16_mfma"]}.get(dom.rsplit("_", 1)[-1], PEAK["fp32_mfma"])
         entry.update(bound="mfma", unit="TFLOP/s", peak=peak, flops_per_launch=flops)
     elif dom in ("weight_step", "weight_prox_f64") and prof["newton_iters"] > 0:
-        # FP64 Newton on the weight prox: per Newton iteration and spectrum the
-        # Hessian build is 2 n 64^2 flop (dense 64 x 64), gradient and line-search
-        # evaluations ~6 n k; averaged over the launches that were timed.
-        launches = prof["weight_step"][1] + prof["weight_prox_f64"][1]
+        # Newton on the weight prox (FP64 arithmetic): per Newton iteration and
+        # spectrum the Hessian build is 2 n 64^2 flop (dense 64 x 64), gradient and
+        # line-search evaluations ~6 n k; the Newton iterations of this kernel
+        # (FP32- or FP64-state) over its timed launches.
+        nit = prof["newton_iters_fp32"] if dom == "weight_step" else prof["newton_iters_fp64"]
         per_newton = 2.0 * n * 64 * 64 + 6.0 * n * k
-        flops = prof["newton_iters"] * per_newton / max(launches, 1)
+        flops = nit * per_newton / max(cnt, 1)
+        entry["kernel"] = "prox_newton_kernel<float, float>" if dom == "weight_step" else \
+            "prox_newton_kernel<double, double>"
         entry.update(bound="alu", unit="TFLOP/s", peak=PEAK["fp64_vector"], flops_per_launch=flops)
     else:
         flops = 2.0 * B * n * k
@@ -93,6 +124,92 @@ def roofline(prof, B, n, k, phi):
     entry["achieved"] = entry["flops_per_launch"] / (ms * 1e-3) / 1e12
     entry["frac"] = entry["achieved"] / entry["peak"]
     return entry
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    times = []
+    out = None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return 1e3 * statistics.median(times), [1e3 * t for t in times], out
+
+
+def oracle_reference(orc, C, wl, D, Y):
+    """FP64 oracle fixed points of the rows of Y (exact weight prox, tol 1e-10)."""
+    K = orc.gibbs_kernel(C, wl.eps)
+    t0 = time.perf_counter()
+    ref = orc.solve(K, D.astype(np.float64), Y.astype(np.float64), fit=wl.fit, pen=wl.pen, eps=wl.eps, lam=wl.lam,
+                    alpha=wl.alpha, max_iter=600, tol=1e-10, mode="exact")
+    return ref["W"], time.perf_counter() - t0
+
+
+def check(W, ref):
+    err = np.linalg.norm(W.astype(np.float64) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return {"fraction": float(np.mean(err <= 1e-5)), "max_err": float(err.max()), "median_err": float(np.median(err))}
+
+
+def train_network(args, otlm, synth, warmstart, torch, kern, Dt, log):
+    """Training triples from the solver, then GPU training; returns (net, info)."""
+    tr = synth.CONFIG5_TRAIN
+    dic = tr.dictionary()
+    info = {"train_spectra": args.train, "epochs": args.epochs, "batch": 256, "lr": 1e-3, "weight_decay": 1e-4,
+            "loss_weights": "log u 0, log v 1, w 16"}
+    t0 = time.perf_counter()
+    Yt = tr.targets_fast(range(args.train), dic=dic, device="cuda:0")
+    torch.cuda.synchronize()
+    info["generate_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p = otlm.SolveParams(eps=tr.eps, fit=tr.fit, pen=tr.pen, lam=tr.lam, alpha=tr.alpha, check_every=5,
+                         max_iter=400, wstep="exact", inner_max=5, tol=1e-8, bulk_tol=1e-4, refine="fp64",
+                         refine_sweeps=300)
+    out = warmstart.solve_in_chunks(kern, Dt, Yt, p)
+    torch.cuda.synchronize()
+    info["solve_s"] = time.perf_counter() - t0
+    info["solve_converged_fraction"] = float((out["status"] & otlm.STATUS_CONVERGED > 0).float().mean())
+    T = warmstart.training_targets(out)
+    del out
+    n = tr.n
+    dims = (n, 512, 512, 2 * n + tr.k)
+    net = otlm.WarmStartMLP(dims, synth.mlp_init(dims, 21))
+    net.set_norm(Yt, T)
+    net.set_loss_weights(np.concatenate([np.zeros(n), np.ones(n), np.full(tr.k, 16.0)]).astype(np.float32))
+    t0 = time.perf_counter()
+    hist = warmstart.train(net, Yt, T, args.epochs, batch=256, lr=1e-3, weight_decay=1e-4, seed=1)
+    torch.cuda.synchronize()
+    info["train_s"] = time.perf_counter() - t0
+    info["loss_first_last_epoch"] = [hist[0], hist[-1]]
+    log(f"# network: {info['train_spectra']} triples solved in {info['solve_s']:.1f} s, "
+        f"{args.epochs} epochs in {info['train_s']:.1f} s, loss {hist[0]:.4g} -> {hist[-1]:.4g}")
+    return net, info
+
+
+def batched_row(args, otlm, synth, torch, orc):
+    """The batched workload (eps = 0.005), cold FP32 bulk + FP64 refinement."""
+    wl = synth.CONFIG2
+    dic = wl.dictionary()
+    D = dic.D.astype(np.float32)
+    Y = wl.targets(dic=dic).astype(np.float32)
+    C = wl.cost()
+    kern = otlm.GibbsKernel(torch.as_tensor(C, device="cuda:0"), wl.eps)
+    Dt, Yt = torch.as_tensor(D, device="cuda:0"), torch.as_tensor(Y, device="cuda:0")
+    p = arm_params("fp32_64_cold", wl, otlm)
+    ms, _, out = timed(lambda: kern.solve(Dt, Yt, p), max(1, min(args.steps, 3)), args.warmup, torch)
+    row = {"workload": wl.name, "B": wl.B, "n": wl.n, "k": wl.k, "eps": wl.eps, "arm": "fp32_64_cold",
+           "ms_per_solve": ms, "iters_mean": float(out["iters"].float().mean())}
+    if orc is not None:
+        pick = np.sort(np.random.default_rng(3).choice(wl.B, 4, replace=False))
+        ref, _ = oracle_reference(orc, C, wl, D, Y[pick])
+        row["check"] = check(out["W"].cpu().numpy()[pick], ref)
+        row["spectra_solved_per_s"] = wl.B * row["check"]["fraction"] / (ms * 1e-3)
+    kern.close()
+    return row
 
 
 def ragged_row(args, otlm, synth, torch):
@@ -182,9 +299,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sample", type=int, default=8)
-    ap.add_argument("--arms", default="paper_mm,exact_fp32,exact_bf16_64,exact_fp32_64")
+    ap.add_argument("--train", type=int, default=200_000, help="training triples for the network")
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--save-net", default=None, help="write the trained network to this .npz")
+    ap.add_argument("--load-net", default=None, help="use a network saved by --save-net instead of training")
+    ap.add_argument("--arms", default="paper_mm,fp32_cold,fp32_64_cold,bf16_64_cold,bf16warm_bf16_64,"
+                                      "bf16warm_fp32_64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch row")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload row")
     ap.add_argument("--ragged-only", action="store_true", help="run only the ragged-batch row")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -193,77 +316,76 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2504_04609_amd import otlm, synth
+    from paper_2504_04609_amd import otlm, synth, warmstart
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
 
-    wl = synth.CONFIG2
+    if args.ragged_only:
+        print(json.dumps({"ragged": ragged_row(args, otlm, synth, torch)}), flush=True)
+        return
+
+    wl = synth.CONFIG5_EVAL
     B, n, k = wl.B, wl.n, wl.k
     dic = wl.dictionary()
     D = dic.D.astype(np.float32)
-    Y = wl.targets(dic=dic).astype(np.float32)
     C = wl.cost()
     dev = "cuda:0"
     Dt = torch.as_tensor(D, device=dev)
-    Yt = torch.as_tensor(Y, device=dev)
+    Yt = wl.targets_fast(dic=dic, device=dev)
+    Y = Yt.cpu().numpy()
     kern = otlm.GibbsKernel(torch.as_tensor(C, device=dev), wl.eps)
     phi = kernel_nonzero_fraction(C, wl.eps)
     arms = [a for a in args.arms.split(",") if a]
-    headline = "exact_fp32_64" if "exact_fp32_64" in arms else arms[-1]
+    headline = HEADLINE if HEADLINE in arms else arms[-1]
+    net, net_info = None, None
+    if any("warm" in a for a in arms):
+        if args.load_net:
+            net, net_info = warmstart.load_network(args.load_net), {"loaded_from": args.load_net}
+        else:
+            net, net_info = train_network(args, otlm, synth, warmstart, torch, kern, Dt, log)
+            if args.save_net:
+                warmstart.save_network(net, args.save_net)
 
-    if args.ragged_only:
-        arms = []
     results = {}
     for arm in arms:
         params = arm_params(arm, wl, otlm)
-        for _ in range(args.warmup):
-            kern.solve(Dt, Yt, params)
-        torch.cuda.synchronize()
-        kern.profile(arm == headline)
-        times = []
-        for _ in range(args.steps):
+        if params.warm:
+            fn = lambda p=params: warmstart.warm_solve(kern, net, Dt, Yt, p, n, infer_prec="bf16")  # noqa: E731
+        else:
+            fn = lambda p=params: kern.solve(Dt, Yt, p)  # noqa: E731
+        if arm == headline:  # kernel classes timed with events inside the timed steps
+            for _ in range(args.warmup):
+                fn()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = kern.solve(Dt, Yt, params)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        prof = kern.profile_read() if arm == headline else None
-        kern.profile(False)
+            kern.profile(True)
+            ms, ms_all, out = timed(fn, args.steps, 0, torch)
+            prof = kern.profile_read()
+            kern.profile(False)
+        else:
+            ms, ms_all, out = timed(fn, args.steps, args.warmup, torch)
+            prof = None
         status = out["status"].cpu().numpy()
-        results[arm] = {"ms_median": 1e3 * statistics.median(times), "ms_all": [1e3 * t for t in times],
-                        "W": out["W"].cpu().numpy(), "iters_mean": float(out["iters"].float().mean()),
+        results[arm] = {"ms_median": ms, "ms_all": ms_all, "W": out["W"].cpu().numpy(),
+                        "iters_mean": float(out["iters"].float().mean()),
                         "status_counts": {int(s): int(c) for s, c in zip(*np.unique(status, return_counts=True))},
-                        "prof": prof}
-        print(f"# {arm}: {results[arm]['ms_median']:.1f} ms/solve, mean iters {results[arm]['iters_mean']:.1f}, "
-              f"status {results[arm]['status_counts']}", file=sys.stderr, flush=True)
+                        "fallbacks": int(np.sum(status & otlm.STATUS_FALLBACK > 0)), "prof": prof}
+        log(f"# {arm}: {ms:.1f} ms/solve, mean iters {results[arm]['iters_mean']:.1f}, "
+            f"status {results[arm]['status_counts']}")
+    infer_ms = None
+    if net is not None:
+        infer_ms, _, _ = timed(lambda: net.infer(Yt, n, n, prec="bf16"), 5, 1, torch)
 
     # verification against the oracle on a sample (also the CPU baseline)
-    cpu = None
+    cpu, orc = None, None
     solved = {a: None for a in arms}
     if not args.no_cpu:
         import oracle as orc
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
-        except Exception:
-            cores = os.cpu_count() or 1
         pick = np.sort(np.random.default_rng(3).choice(B, args.sample, replace=False))
-        K = orc.gibbs_kernel(C, wl.eps)
-        t0 = time.perf_counter()
-        ref = orc.solve(K, D.astype(np.float64), Y[pick].astype(np.float64), fit=wl.fit, pen=wl.pen, eps=wl.eps,
-                        lam=wl.lam, alpha=wl.alpha, max_iter=400, tol=1e-10, mode="exact")
-        dt = time.perf_counter() - t0
-        cpu = {"value": args.sample / dt, "unit": "spectra/s", "cores": cores, "kind": "oracle",
-               "sample": f"{args.sample} spectra of the batch (seed 3) solved to tol 1e-10, FP64, exact weight prox",
-               "seconds": dt}
+        ref, dt = oracle_reference(orc, C, wl, D, Y[pick])
+        cpu = {"value": args.sample / dt, "unit": "spectra/s", "cores": cores_used(), "kind": "oracle",
+               "sample": f"{args.sample} held-out spectra (seed 3) solved to tol 1e-10 from a cold start, FP64, "
+                         "exact weight prox", "seconds": dt}
         for arm in arms:
-            w = results[arm]["W"][pick].astype(np.float64)
-            err = np.linalg.norm(w - ref["W"], axis=1) / np.linalg.norm(ref["W"], axis=1)
-            solved[arm] = {"fraction": float(np.mean(err <= 1e-5)), "max_err": float(err.max()),
-                           "median_err": float(np.median(err))}
-
-    ragged = None if args.no_ragged else ragged_row(args, otlm, synth, torch)
-    if args.ragged_only:
-        print(json.dumps({"ragged": ragged}), flush=True)
-        return
+            solved[arm] = check(results[arm]["W"][pick], ref)
 
     def value_of(arm):
         frac = solved[arm]["fraction"] if solved[arm] is not None else float("nan")
@@ -281,23 +403,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "bf16+f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "B": B, "n": n, "k": k, "eps": wl.eps, "datafit": "kl", "lambda": wl.lam,
-                   "penalty": "l1", "alpha": wl.alpha, "arm": headline, "start": "cold",
+                   "penalty": "l1", "alpha": wl.alpha, "arm": headline, "warm_probe": PROBE,
                    "solved_criterion": "rel l2 weight error <= 1e-5 vs FP64 oracle (tol 1e-10), sampled"},
-        "roofline": roofline(h["prof"], B, n, k, phi),
+        "roofline": roofline(h["prof"], B, n, k, phi) if h["prof"] else None,
         "arms": {a: {"ms_per_solve": r["ms_median"], "spectra_solved_per_s": value_of(a),
-                     "iters_mean": r["iters_mean"], "status_counts": r["status_counts"], "check": solved[a]}
-                 for a, r in results.items()},
-        "kernels_ms_per_launch": {c: v[0] for c, v in h["prof"].items() if isinstance(v, tuple) and v[1]},
-        "kernel_launches": {c: v[1] for c, v in h["prof"].items() if isinstance(v, tuple) and v[1]},
+                     "iters_mean": r["iters_mean"], "status_counts": r["status_counts"],
+                     "fallbacks": r["fallbacks"], "check": solved[a]} for a, r in results.items()},
         "nonzero_fraction_K": phi,
     }
+    if h["prof"]:
+        line["kernels_ms_per_launch"] = {c: v[0] for c, v in h["prof"].items() if isinstance(v, tuple) and v[1]}
+        line["kernel_launches"] = {c: v[1] for c, v in h["prof"].items() if isinstance(v, tuple) and v[1]}
+        line["newton_iters"] = h["prof"]["newton_iters"]
+    for base in (BASELINE_ARM, "fp32_cold"):
+        if base in results and solved[base] and solved[headline] and value_of(base) > 0:
+            line[f"speedup_vs_{base}"] = value_of(headline) / value_of(base)
+    if net_info is not None:
+        net_info["bf16_infer_ms"] = infer_ms
+        line["network"] = net_info
     if cpu is not None:
         line["cpu_baseline"] = cpu
-    if ragged is not None:
-        line["ragged"] = ragged
+    if not args.no_batched:
+        line["batched"] = batched_row(args, otlm, synth, torch, orc)
+    if not args.no_ragged:
+        line["ragged"] = ragged_row(args, otlm, synth, torch)
     print(json.dumps(line), flush=True)
 
 

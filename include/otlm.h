@@ -81,8 +81,12 @@ enum {
   OTLM_S_NONFINITE = 4,   /* a NaN/Inf appeared; the spectrum was frozen             */
   OTLM_S_STAGNATED = 8,   /* the weight change stopped improving for 6 tests: the
                              noise floor of the phase precision was reached        */
-  OTLM_S_FALLBACK = 16    /* (with another flag) the warm start failed the probe
+  OTLM_S_FALLBACK = 16,   /* (with another flag) the warm start failed the probe
                              and the spectrum was solved from the cold start       */
+  OTLM_S_ABSORBED = 32    /* (with another flag) the scalings of the FP32 bulk
+                             phase exceeded exp(+-absorb_tau); the spectrum left
+                             the bulk phase early and was solved in the FP64
+                             state                                                */
 };
 
 /* Solver parameters.  A solve has a bulk phase in precision `prec` and, when
@@ -109,6 +113,11 @@ typedef struct {
                             exceeds warm_probe relative to max|w| (or is not
                             finite) restarts from the cold start and is flagged
                             OTLM_S_FALLBACK; 0: no probe                          */
+  double absorb_tau;     /* with REFINE_FP64: at every convergence test of the
+                            bulk phase a spectrum with |log u_i| or |log v_i| >
+                            absorb_tau moves to the FP64 phase (whose state spans
+                            exp(+-709)) and is flagged OTLM_S_ABSORBED; 0: off;
+                            default 30                                            */
   int32_t max_iter;      /* iteration cap of the bulk phase, >= 1                  */
   int32_t check_every;   /* convergence test cadence in iterations, >= 1           */
   int32_t fit;           /* otlm_datafit                                           */
@@ -129,7 +138,7 @@ typedef struct {
 } otlm_params;
 
 /* Fill `p` with defaults: KL datafit, no penalty, eps = lambda = 1, tol 1e-6,
- * bulk_tol 1e-4, max_iter 1000, check_every 10, FP32, no refinement
+ * bulk_tol 1e-4, absorb_tau 30, no warm probe, max_iter 1000, check_every 10, FP32, no refinement
  * (refine_sweeps 200 when enabled), cold start, one MM step per iteration,
  * inner_max 5. */
 void otlm_default_params(otlm_params* p);
@@ -199,18 +208,21 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
 
 /* Kernel timing on the solve's own stream.  While enabled, otlm_solve_batch
  * brackets every launch of its hot kernels with HIP events and accumulates
- * their durations per kernel class (11 classes):
+ * their durations per kernel class (12 classes):
  *   [0] s = K v product, FP32 (+ log-ratio epilogue)
- *   [1] weight step, FP32 state (MM GEMM epilogue or the Newton prox kernel)
+ *   [1] weight step, FP32 state: the MM GEMM epilogue (WSTEP_MM) or the
+ *       Newton prox kernel (WSTEP_EXACT)
  *   [2] a = D w, u = a / s, FP32        [3] t = K^T u product + prox, FP32
  *   [4] convergence test
  *   [5]..[8] the same as [0]..[3] in the FP64 refinement phase
  *   [9] s = K v product in BF16 (FP32 accumulate)  [10] t = K^T u in BF16
- * otlm_profile_read copies the mean duration in ms per launch (ms[11]) and the
- * launch counts (count[11]) accumulated since the last enable, synchronising
+ *   [11] MM warm-up steps of an exact-prox solve (cold starts, fallbacks)
+ * otlm_profile_read copies the mean duration in ms per launch (ms[12]) and the
+ * launch counts (count[12]) accumulated since the last enable, synchronising
  * the recorded events first, and the Newton iterations the weight-prox
- * kernels performed, summed over spectra (*newton_iters; a profiled solve
- * synchronises its stream at the end to collect them).  Any output pointer
+ * kernels performed, summed over spectra (newton_iters[2]: FP32-state kernel,
+ * FP64-state kernel; a profiled solve synchronises its stream at the end to
+ * collect them).  Any output pointer
  * may be NULL.  Enabling resets the counters.  Errors: OTLM_E_INVALID for a
  * null kernel. */
 int otlm_profile_enable(otlm_kernel k, int32_t on);
@@ -343,6 +355,12 @@ int otlm_mlp_set_norm(otlm_mlp m, const float* X, const float* T, int64_t N, voi
  * Synchronises `stream`.  Errors: OTLM_E_INVALID for a negative or non-finite
  * weight. */
 int otlm_mlp_set_loss_weights(otlm_mlp m, const float* weights, void* stream);
+
+/* Set the standardisation statistics directly (host or device FP32 [in] and
+ * [out]; standard deviations > 0), e.g. to restore a saved network.
+ * Synchronises `stream`. */
+int otlm_mlp_set_norm_stats(otlm_mlp m, const float* in_mu, const float* in_sd, const float* out_mu,
+                            const float* out_sd, void* stream);
 
 /* Copy the standardisation statistics out (any pointer may be NULL). */
 int otlm_mlp_get_norm(otlm_mlp m, float* in_mu, float* in_sd, float* out_mu, float* out_sd, void* stream);

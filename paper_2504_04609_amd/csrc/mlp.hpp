@@ -221,6 +221,27 @@ int otlm_mlp_set_loss_weights(otlm_mlp m, const float* weights, void* stream) {
   return OTLM_OK;
 }
 
+int otlm_mlp_set_norm_stats(otlm_mlp m, const float* in_mu, const float* in_sd, const float* out_mu,
+                            const float* out_sd, void* stream) {
+  if (!m || !in_mu || !in_sd || !out_mu || !out_sd) return OTLM_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bi = (size_t)m->dims[0] * sizeof(float), bo = (size_t)m->dims[3] * sizeof(float);
+  std::vector<float> sd((size_t)std::max(m->dims[0], m->dims[3]));
+  for (int pass = 0; pass < 2; ++pass) {  // standard deviations must be positive and finite
+    const size_t cnt = pass ? (size_t)m->dims[3] : (size_t)m->dims[0];
+    OTLM_HIP(hipMemcpyAsync(sd.data(), pass ? out_sd : in_sd, cnt * sizeof(float), hipMemcpyDefault, s));
+    OTLM_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < cnt; ++i)
+      if (!(sd[i] > 0.f) || !std::isfinite(sd[i])) return OTLM_E_INVALID;
+  }
+  OTLM_HIP(hipMemcpyAsync(m->in_mu, in_mu, bi, hipMemcpyDefault, s));
+  OTLM_HIP(hipMemcpyAsync(m->in_sd, in_sd, bi, hipMemcpyDefault, s));
+  OTLM_HIP(hipMemcpyAsync(m->out_mu, out_mu, bo, hipMemcpyDefault, s));
+  OTLM_HIP(hipMemcpyAsync(m->out_sd, out_sd, bo, hipMemcpyDefault, s));
+  OTLM_HIP(hipStreamSynchronize(s));
+  return OTLM_OK;
+}
+
 int otlm_mlp_get_norm(otlm_mlp m, float* in_mu, float* in_sd, float* out_mu, float* out_sd, void* stream) {
   if (!m) return OTLM_E_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -54,9 +54,10 @@ struct Workspace {
   float* ew_prev = nullptr;
   float* ew_best = nullptr;
   int* stall = nullptr;
-  int* nit = nullptr;
+  int* nit = nullptr;    // Newton iterations per spectrum, FP32-state prox
+  int* nit64 = nullptr;  // the same, FP64-state prox
   int* mm_until = nullptr;  // last iteration of each spectrum's MM warm-up (exact weight prox)
-  int* fallback = nullptr;  // 1 when a warm start was replaced by the cold start
+  int* xflags = nullptr;    // status bits set on the way: 16 warm start replaced, 32 range promotion
   int* it_base = nullptr;   // per-spectrum offset of refinement-phase iteration indices
   unsigned short *Vbf = nullptr, *Ubf = nullptr;
   // FP64 refinement state
@@ -81,8 +82,8 @@ struct Workspace {
     ew_prev = nullptr;
     ew_best = nullptr;
     stall = nullptr;
-    nit = nullptr;
-    mm_until = fallback = it_base = nullptr;
+    nit = nit64 = nullptr;
+    mm_until = xflags = it_base = nullptr;
     Vbf = Ubf = nullptr;
   }
   void release64() {
@@ -116,7 +117,7 @@ constexpr float OTLM_BF16_FLOOR = 3.0e-4f;         // ~2^-12: BF16 products move
 constexpr int MAX_TILES = 256;
 // kernel classes timed by otlm_profile_* (order documented in include/otlm.h)
 enum { PROF_KV32 = 0, PROF_W32, PROF_U32, PROF_KTU32, PROF_CHECK, PROF_KV64, PROF_W64, PROF_U64, PROF_KTU64,
-       PROF_KVBF, PROF_KTUBF, OTLM_PROF_CLASSES };  // per-row partial slots: np / 64 <= 256 column tiles
+       PROF_KVBF, PROF_KTUBF, PROF_WMM32, OTLM_PROF_CLASSES };  // per-row partial slots: np / 64 <= 256 column tiles
 
 }  // namespace
 
@@ -141,7 +142,7 @@ struct otlm_kernel_s {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double prof_ms[OTLM_PROF_CLASSES] = {};
   int64_t prof_n[OTLM_PROF_CLASSES] = {};
-  int64_t prof_newton = 0;  // Newton iterations of the weight-prox kernels (summed over spectra)
+  int64_t prof_newton[2] = {0, 0};  // Newton iterations of the weight prox, FP32 / FP64 state (summed over spectra)
 };
 
 namespace {
@@ -184,8 +185,9 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.ew_best, (size_t)B);
   rc |= dev_alloc(ws, &ws.stall, (size_t)B);
   rc |= dev_alloc(ws, &ws.nit, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nit64, (size_t)B);
   rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
-  rc |= dev_alloc(ws, &ws.fallback, (size_t)B);
+  rc |= dev_alloc(ws, &ws.xflags, (size_t)B);
   rc |= dev_alloc(ws, &ws.it_base, (size_t)B);
   rc |= dev_alloc(ws, &ws.Vbf, bn);
   rc |= dev_alloc(ws, &ws.Ubf, bn);
@@ -272,7 +274,7 @@ bool params_valid(const otlm_params* p, double kernel_eps) {
   if (p->prec != OTLM_PREC_FP32 && p->prec != OTLM_PREC_BF16) return false;
   if (p->refine < OTLM_REFINE_NONE || p->refine > OTLM_REFINE_FP64) return false;
   if (p->refine != OTLM_REFINE_NONE && p->refine_sweeps < 1) return false;
-  if (!(p->bulk_tol >= 0.0) || !(p->warm_probe >= 0.0)) return false;
+  if (!(p->bulk_tol >= 0.0) || !(p->warm_probe >= 0.0) || !(p->absorb_tau >= 0.0)) return false;
   return true;
 }
 
@@ -294,6 +296,7 @@ void otlm_default_params(otlm_params* p) {
   p->refine = OTLM_REFINE_NONE;
   p->refine_sweeps = 200;
   p->bulk_tol = 1e-4;
+  p->absorb_tau = 30.0;
   p->wstep = OTLM_WSTEP_MM;
   p->inner_max = 5;
 }
@@ -392,7 +395,7 @@ int otlm_profile_enable(otlm_kernel k, int32_t on) {
     k->prof_ms[c] = 0.0;
     k->prof_n[c] = 0;
   }
-  k->prof_newton = 0;
+  k->prof_newton[0] = k->prof_newton[1] = 0;
   k->profile = on != 0;
   return OTLM_OK;
 }
@@ -400,7 +403,10 @@ int otlm_profile_enable(otlm_kernel k, int32_t on) {
 int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton_iters) {
   if (!k) return OTLM_E_INVALID;
   prof_collect(k);
-  if (newton_iters) *newton_iters = k->prof_newton;
+  if (newton_iters) {
+    newton_iters[0] = k->prof_newton[0];
+    newton_iters[1] = k->prof_newton[1];
+  }
   for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     if (ms) ms[c] = k->prof_n[c] ? k->prof_ms[c] / (double)k->prof_n[c] : 0.0;
     if (count) count[c] = k->prof_n[c];
@@ -475,14 +481,17 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
 
   OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
-  if (exact) OTLM_HIP(hipMemsetAsync(ws.nit, 0, (size_t)B * sizeof(int), s));
+  if (exact) {
+    OTLM_HIP(hipMemsetAsync(ws.nit, 0, (size_t)B * sizeof(int), s));
+    OTLM_HIP(hipMemsetAsync(ws.nit64, 0, (size_t)B * sizeof(int), s));
+  }
   OTLM_HIP(hipMemsetAsync(ws.it_base, 0, (size_t)B * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
                      p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
                      (const float4*)ws.colc, (int)n, (int)kdim, (int)np, (int)kp, p->warm, ws.V, ws.W, ws.U,
                      ws.done, ws.status, ws.iters, ws.ew_prev, ws.ew_best, ws.stall, ws.mm_until,
-                     exact ? OTLM_MM_WARMUP : 0, ws.fallback, ws.flags + 1);
+                     exact ? OTLM_MM_WARMUP : 0, ws.xflags, ws.flags + 1);
   OTLM_HIP(hipGetLastError());
   OTLM_HIP(hipMemcpyAsync(ws.host_flags, ws.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   OTLM_HIP(hipStreamSynchronize(s));
@@ -528,7 +537,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.mm_until = nullptr; a.it = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
-    a.nit = ws.nit;
+    a.nit = ws.nit64;
     return a;
   };
 
@@ -559,7 +568,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS), prox_newton_smem((int)n, sizeof(float)), s, a);
     }
     if (mm_step) {  // MM weight step (every spectrum, or those in their warm-up)
-      ProfScope ps(k, PROF_W32, s);
+      ProfScope ps(k, exact ? PROF_WMM32 : PROF_W32, s);
       GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
       EpiWupd e{ws.W, ws.colc, ws.done, exact ? ws.mm_until : nullptr, it, (int)kp, (int)kdim, p->pen, false};
       gemm(64, bn_w, g, e, s);
@@ -626,6 +635,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W, (int)kp, (int)kdim, M, ws.Wsnap, init, ws.pwn, ws.pwd);
     }
   };
+  // range promotion of the FP32 bulk phase (needs the FP64 phase to continue in)
+  const bool absorb = fp64 && p->absorb_tau > 0.0;
   // probe: test the warm start at the first convergence test of this phase
   auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase,
                        bool probe) -> int {
@@ -651,8 +662,12 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
                              (const float*)ws.pwd, (float)p->warm_probe, Y, (const float4*)ws.colc, (int)n,
                              (int)kdim, (int)np, (int)kp, it, exact ? OTLM_MM_WARMUP : 0, ws.V,
                              bf16 ? ws.Vbf : nullptr, ws.W, ws.Wsnap, ws.U, ws.done, ws.status, ws.ew_prev,
-                             ws.ew_best, ws.stall, ws.mm_until, ws.fallback, ws.flags + 2);
+                             ws.ew_best, ws.stall, ws.mm_until, ws.xflags, ws.flags + 2);
         first_check = false;
+        if (absorb && !use64)
+          hipLaunchKernelGGL(range_check, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, (const float*)ws.U,
+                             (const float*)ws.V, (int)n, (int)np, M, (float)p->absorb_tau, it, ws.done, ws.status,
+                             ws.iters, ws.xflags, ws.flags);
         if (hipGetLastError() != hipSuccess) return OTLM_E_HIP;
         if (hipMemcpyAsync(ws.host_flags, ws.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -704,16 +719,19 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
   if (state64)
     hipLaunchKernelGGL(write_outputs64, dim3((unsigned)B), dim3(256), 0, s, ws.W64, ws.U64, ws.V64, ws.done,
-                       ws.status, ws.iters, (const int*)ws.fallback, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.status, ws.iters, (const int*)ws.xflags, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   else
     hipLaunchKernelGGL(write_outputs, dim3((unsigned)B), dim3(256), 0, s, ws.W, ws.U, ws.V, ws.done, ws.status,
-                       ws.iters, (const int*)ws.fallback, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
+                       ws.iters, (const int*)ws.xflags, (const int*)ws.it_base, (int)n, (int)kdim, (int)np, (int)kp, last, W, logU, logV, iters, status);
   OTLM_HIP(hipGetLastError());
   if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
     std::vector<int> h((size_t)B);
+    std::vector<int> h64((size_t)B);
     OTLM_HIP(hipMemcpyAsync(h.data(), ws.nit, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipMemcpyAsync(h64.data(), ws.nit64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipStreamSynchronize(s));
-    for (int v : h) k->prof_newton += v;
+    for (int v : h) k->prof_newton[0] += v;
+    for (int v : h64) k->prof_newton[1] += v;
   }
   return OTLM_OK;
 }

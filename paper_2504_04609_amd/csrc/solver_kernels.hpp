@@ -289,7 +289,7 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
                            float* __restrict__ U, int* __restrict__ done, int* __restrict__ status,
                            int* __restrict__ iters, float* __restrict__ ew_prev, float* __restrict__ ew_best,
                            int* __restrict__ stall, int* __restrict__ mm_until, int mm_warmup,
-                           int* __restrict__ fallback, int* __restrict__ bad) {
+                           int* __restrict__ xflags, int* __restrict__ bad) {
   const int b = blockIdx.x;
   __shared__ double ssum[256];
   double acc = 0.0;
@@ -325,22 +325,23 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
     ew_best[b] = INFINITY;
     stall[b] = 0;
     mm_until[b] = warm ? 0 : mm_warmup;
-    fallback[b] = 0;
+    xflags[b] = 0;
   }
 }
 
 // Fallback of a warm start: at the first convergence test, a spectrum whose
 // weight change over the interval exceeds `probe` relative to max|w| (or is
 // not finite) is restarted from the cold start (v = 1, w0_j = sum(y)/(k x_j),
-// u = 0), takes MM steps up to iteration it + mm_warmup, and is flagged.  The
-// caller recomputes a = D w afterwards.  One workgroup per spectrum.
+// u = 0), takes MM steps up to iteration it + mm_warmup, and is flagged (bit
+// 16 of xflags).  The caller recomputes a = D w afterwards.  One workgroup per
+// spectrum.
 __global__ void warm_fallback(const float* __restrict__ pwn, const float* __restrict__ pwd, float probe,
                               const float* __restrict__ Y, const float4* __restrict__ colc, int n, int k, int np,
                               int kp, int it, int mm_warmup, float* __restrict__ V, unsigned short* __restrict__ Vbf,
                               float* __restrict__ W, float* __restrict__ Wsnap, float* __restrict__ U,
                               int* __restrict__ done, int* __restrict__ status, float* __restrict__ ew_prev,
                               float* __restrict__ ew_best, int* __restrict__ stall, int* __restrict__ mm_until,
-                              int* __restrict__ fallback, int* __restrict__ count) {
+                              int* __restrict__ xflags, int* __restrict__ count) {
   const int b = blockIdx.x;
   const float d = pwd[b] > 0.f ? pwn[b] / pwd[b] : 0.f;
   if (d <= probe) return;  // also skips nothing for NaN: NaN fails the comparison and falls back
@@ -372,8 +373,36 @@ __global__ void warm_fallback(const float* __restrict__ pwn, const float* __rest
     ew_best[b] = INFINITY;
     stall[b] = 0;
     mm_until[b] = it + mm_warmup;
-    fallback[b] = 1;
+    xflags[b] |= 16;
     atomicAdd(count, 1);
+  }
+}
+
+// Scaling range test of a bulk phase (FP32 state): an active spectrum with
+// |log u_i| > tau or |log v_i| > tau for some bin stops its bulk phase and
+// continues in the FP64 phase, whose state has the range of exp(+-709); it is
+// flagged (bit 32 of xflags) and leaves the active count.  One wave per
+// spectrum.
+__global__ __launch_bounds__(256) void range_check(const float* __restrict__ U, const float* __restrict__ V, int n,
+                                                   int np, int B, float tau, int it, int* __restrict__ done,
+                                                   int* __restrict__ status, int* __restrict__ iters,
+                                                   int* __restrict__ xflags, int* __restrict__ active) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b >= B || done[b]) return;
+  float m = 0.f;
+  for (int i = lane; i < n; i += 64) {
+    const float u = U[(size_t)b * np + i], v = V[(size_t)b * np + i];
+    if (u > 0.f) m = fmaxf(m, fabsf(logf(u)));
+    if (v > 0.f) m = fmaxf(m, fabsf(logf(v)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if (lane == 0 && m > tau) {
+    done[b] = 1;
+    status[b] = 32;
+    iters[b] = it;
+    xflags[b] |= 32;
+    atomicSub(active, 1);
   }
 }
 
@@ -487,7 +516,7 @@ __global__ void check_convergence(const float* __restrict__ psn, const float* __
 __global__ void write_outputs(const float* __restrict__ Wst, const float* __restrict__ U,
                               const float* __restrict__ V, const int* __restrict__ done,
                               const int* __restrict__ st, const int* __restrict__ it_in,
-                              const int* __restrict__ fallback, const int* __restrict__ it_base, int n, int k,
+                              const int* __restrict__ xflags, const int* __restrict__ it_base, int n, int k,
                               int np, int kp, int max_iter, float* __restrict__ W, float* __restrict__ logU,
                               float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
   const int b = blockIdx.x;
@@ -498,6 +527,6 @@ __global__ void write_outputs(const float* __restrict__ Wst, const float* __rest
   }
   if (threadIdx.x == 0) {
     if (iters) iters[b] = done[b] ? it_in[b] : max_iter + it_base[b];
-    if (status) status[b] = (done[b] ? st[b] : 2) | (fallback[b] ? 16 : 0);
+    if (status) status[b] = (done[b] ? st[b] : 2) | xflags[b];
   }
 }

@@ -128,7 +128,7 @@ __global__ void convert_f32_to_f64(const float* __restrict__ x, double* __restri
 __global__ void write_outputs64(const double* __restrict__ Wst, const double* __restrict__ U,
                                 const double* __restrict__ V, const int* __restrict__ done,
                                 const int* __restrict__ st, const int* __restrict__ it_in,
-                                const int* __restrict__ fallback, const int* __restrict__ it_base, int n, int k,
+                                const int* __restrict__ xflags, const int* __restrict__ it_base, int n, int k,
                                 int np, int kp, int last_iter, float* __restrict__ W, float* __restrict__ logU,
                                 float* __restrict__ logV, int* __restrict__ iters, int* __restrict__ status) {
   const int b = blockIdx.x;
@@ -139,7 +139,7 @@ __global__ void write_outputs64(const double* __restrict__ Wst, const double* __
   }
   if (threadIdx.x == 0) {
     if (iters) iters[b] = done[b] ? it_in[b] : last_iter + it_base[b];
-    if (status) status[b] = (done[b] ? st[b] : 2) | (fallback[b] ? 16 : 0);
+    if (status) status[b] = (done[b] ? st[b] : 2) | xflags[b];
   }
 }
 

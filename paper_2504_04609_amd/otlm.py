@@ -20,17 +20,19 @@ PREC = {"fp32": 0, "bf16": 1}
 REFINE = {"none": 0, "fp32": 1, "fp64": 2}
 WSTEP = {"mm": 0, "exact": 1}
 
-STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED, STATUS_FALLBACK = 1, 2, 4, 8, 16
+STATUS_CONVERGED, STATUS_MAX_ITER, STATUS_NONFINITE, STATUS_STAGNATED = 1, 2, 4, 8
+STATUS_FALLBACK, STATUS_ABSORBED = 16, 32
 
 EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm_kernel_info",
             "otlm_solve_batch", "otlm_objective", "otlm_status_str", "otlm_profile_enable",
             "otlm_profile_read", "otlm_ragged_default_opts", "otlm_ragged_create", "otlm_ragged_solve",
             "otlm_ragged_info", "otlm_ragged_profile_enable", "otlm_ragged_profile_read", "otlm_ragged_free",
-            "otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_set_loss_weights", "otlm_mlp_get_norm", "otlm_mlp_grad",
+            "otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_set_loss_weights",
+            "otlm_mlp_set_norm_stats", "otlm_mlp_get_norm", "otlm_mlp_grad",
             "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer", "otlm_mlp_free")
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
                    "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
-                   "kv_product_bf16", "ktu_product_bf16")
+                   "kv_product_bf16", "ktu_product_bf16", "weight_mm_warmup")
 RAGGED_PROFILE_CLASSES = ("kv_product", "weight_step", "ktu_product", "convergence_test")
 RAGGED_TILES = ((128, 128), (128, 64), (64, 128), (64, 64))
 
@@ -42,7 +44,7 @@ class OtlmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("lambda_", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double),
-                ("bulk_tol", ctypes.c_double), ("warm_probe", ctypes.c_double),
+                ("bulk_tol", ctypes.c_double), ("warm_probe", ctypes.c_double), ("absorb_tau", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("fit", ctypes.c_int32),
                 ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32), ("wstep", ctypes.c_int32),
@@ -97,6 +99,7 @@ def load() -> ctypes.CDLL:
     lib.otlm_mlp_set_norm.argtypes = [vp, vp, vp, i64, vp]
     lib.otlm_mlp_get_norm.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.otlm_mlp_set_loss_weights.argtypes = [vp, vp, vp]
+    lib.otlm_mlp_set_norm_stats.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.otlm_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     lib.otlm_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(AdamW), vp, vp]
     lib.otlm_mlp_get_params.argtypes = [vp, vp, vp]
@@ -104,7 +107,7 @@ def load() -> ctypes.CDLL:
     lib.otlm_mlp_infer.argtypes = [vp, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
     lib.otlm_mlp_free.argtypes = [vp]
     for name in ("otlm_mlp_create", "otlm_mlp_info", "otlm_mlp_set_norm", "otlm_mlp_set_loss_weights",
-                 "otlm_mlp_get_norm", "otlm_mlp_grad",
+                 "otlm_mlp_set_norm_stats", "otlm_mlp_get_norm", "otlm_mlp_grad",
                  "otlm_mlp_train_step", "otlm_mlp_get_params", "otlm_mlp_set_params", "otlm_mlp_infer",
                  "otlm_mlp_free"):
         getattr(lib, name).restype = ctypes.c_int
@@ -141,6 +144,7 @@ class SolveParams:
     bulk_tol: float = 1e-4
     warm: bool = False
     warm_probe: float = 0.0     # > 0: cold restart of warm starts whose first interval moves w more
+    absorb_tau: float = 30.0    # FP64 refinement: move spectra with |log u| or |log v| above it to FP64
     wstep: str = "mm"           # "mm" (one MM step, Algorithm 1) or "exact" (ProxP by Newton)
     inner_max: int = 5
 
@@ -154,6 +158,7 @@ class SolveParams:
         p.refine, p.refine_sweeps = REFINE[self.refine], self.refine_sweeps
         p.warm = int(self.warm)
         p.warm_probe = self.warm_probe
+        p.absorb_tau = self.absorb_tau
         p.wstep, p.inner_max = WSTEP[self.wstep], self.inner_max
         return p
 
@@ -202,10 +207,11 @@ class GibbsKernel:
         """Mean ms per launch and launch count for each timed kernel class."""
         ms = (ctypes.c_double * len(PROFILE_CLASSES))()
         cnt = (ctypes.c_int64 * len(PROFILE_CLASSES))()
-        nit = ctypes.c_int64()
-        _check(load().otlm_profile_read(self.handle, ms, cnt, ctypes.byref(nit)), "otlm_profile_read")
+        nit = (ctypes.c_int64 * 2)()
+        _check(load().otlm_profile_read(self.handle, ms, cnt, nit), "otlm_profile_read")
         out = {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_CLASSES)}
-        out["newton_iters"] = nit.value
+        out["newton_iters"] = nit[0] + nit[1]
+        out["newton_iters_fp32"], out["newton_iters_fp64"] = nit[0], nit[1]
         return out
 
     def close(self):
@@ -399,6 +405,15 @@ class WarmStartMLP:
             raise OtlmError(f"weights must have shape ({self.dims[3]},)")
         _check(load().otlm_mlp_set_loss_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
                "otlm_mlp_set_loss_weights")
+
+    def set_norm_stats(self, in_mu, in_sd, out_mu, out_sd, stream=None):
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (in_mu, in_sd, out_mu, out_sd)]
+        if arrs[0].shape != (self.dims[0],) or arrs[1].shape != (self.dims[0],) or \
+                arrs[2].shape != (self.dims[3],) or arrs[3].shape != (self.dims[3],):
+            raise OtlmError("standardisation statistics have the wrong shapes")
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        _check(load().otlm_mlp_set_norm_stats(self.handle, *ptrs, _stream(stream)), "otlm_mlp_set_norm_stats")
 
     def get_norm(self, stream=None):
         import torch

@@ -58,6 +58,23 @@ def train(net, X, T, epochs: int, batch: int = 256, lr: float = 1e-3, lr_min: fl
     return history
 
 
+def save_network(net, path):
+    """Parameters and standardisation of a network, as an .npz file."""
+    import numpy as np
+    i_mu, i_sd, o_mu, o_sd = [t.cpu().numpy() for t in net.get_norm()]
+    np.savez(path, dims=np.array(net.dims, dtype=np.int32), theta=net.params().cpu().numpy(), in_mu=i_mu,
+             in_sd=i_sd, out_mu=o_mu, out_sd=o_sd)
+
+
+def load_network(path):
+    """A network written by save_network (no pickled objects are read)."""
+    import numpy as np
+    with np.load(path, allow_pickle=False) as f:
+        net = otlm.WarmStartMLP(tuple(int(d) for d in f["dims"]), f["theta"])
+        net.set_norm_stats(f["in_mu"], f["in_sd"], f["out_mu"], f["out_sd"])
+    return net
+
+
 def warm_solve(kern, net, D, Y, params, n: int, infer_prec: str = "bf16"):
     """Predict (log v, w) with the network, then solve from there; params must
     have warm=True (and usually warm_probe > 0)."""

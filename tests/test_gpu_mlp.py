@@ -159,3 +159,19 @@ def test_training_trajectory_follows_oracle():
     np.testing.assert_allclose(gpu_loss, ref_loss, rtol=1e-2)
     assert rel(net.params().cpu().numpy(), p) <= 1e-2
     assert ref_loss[-1] < 0.5 * ref_loss[0]
+
+
+def test_save_and_load_keep_the_predictions(tmp_path):
+    from paper_2504_04609_amd import warmstart
+    net = otlm.WarmStartMLP(DIMS, synth.mlp_init(DIMS, 16))
+    X, T = data(128, DIMS, 17)
+    net.set_norm(gpu(X), gpu(T))
+    path = str(tmp_path / "net.npz")
+    warmstart.save_network(net, path)
+    net2 = warmstart.load_network(path)
+    Y = gpu(X[:20])
+    a = net.infer(Y, 16, 16, prec="fp32")
+    b = net2.infer(Y, 16, 16, prec="fp32")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+    np.testing.assert_array_equal(a[2].cpu().numpy(), b[2].cpu().numpy())

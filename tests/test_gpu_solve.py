@@ -350,3 +350,22 @@ def test_bf16_bulk_then_fp32_ridge():
                        refine="fp32", refine_sweeps=2000)
     assert np.all(res["status"] == otlm.STATUS_CONVERGED)
     assert rel_err(res["W"], ref["W"]).max() <= 1e-5
+
+
+def test_small_eps_range_promotion_reaches_oracle():
+    """eps = 0.001: BF16 bulk products, FP64 refinement.  With the range test
+    forced low (|log u| > 5, below the |log u| ~ 10-12 these spectra reach) every
+    spectrum leaves the bulk phase early for the FP64 state and still reaches the
+    oracle; with the default threshold (30) none is moved."""
+    wl = synth.CONFIG3
+    idx = [0, 5, 9, 123]
+    D32, Y32, C = setup(wl, idx)
+    common = dict(tol=1e-9, bulk_tol=1e-3, max_iter=400, check_every=5, wstep="exact", inner_max=5, prec="bf16",
+                  refine="fp64", refine_sweeps=300)
+    ref = oracle_solve(C, D32, Y32, wl, max_iter=800, tol=1e-11, mode="exact")
+    _, low = gpu_solve(C, D32, Y32, wl, absorb_tau=5.0, **common)
+    assert (low["status"] & otlm.STATUS_ABSORBED).all() and (low["status"] & otlm.STATUS_CONVERGED).all()
+    assert rel_err(low["W"], ref["W"]).max() <= 1e-5
+    _, std = gpu_solve(C, D32, Y32, wl, **common)
+    assert not (std["status"] & otlm.STATUS_ABSORBED).any() and (std["status"] & otlm.STATUS_CONVERGED).all()
+    assert rel_err(std["W"], ref["W"]).max() <= 1e-5
