@@ -220,8 +220,9 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
  * otlm_profile_read copies the mean duration in ms per launch (ms[12]) and the
  * launch counts (count[12]) accumulated since the last enable, synchronising
  * the recorded events first, and the Newton iterations the weight-prox
- * kernels performed, summed over spectra (newton_iters[2]: FP32-state kernel,
- * FP64-state kernel; a profiled solve synchronises its stream at the end to
+ * kernels performed, summed over spectra (newton_iters[4]: Newton iterations
+ * of the FP32-state and FP64-state kernels, then their Hessian
+ * factorisations; a profiled solve synchronises its stream at the end to
  * collect them).  Any output pointer
  * may be NULL.  Enabling resets the counters.  Errors: OTLM_E_INVALID for a
  * null kernel. */

@@ -56,6 +56,13 @@ struct Workspace {
   int* stall = nullptr;
   int* nit = nullptr;    // Newton iterations per spectrum, FP32-state prox
   int* nit64 = nullptr;  // the same, FP64-state prox
+  int* nfac = nullptr;   // Hessian factorisations per spectrum, FP32-state prox
+  int* nfac64 = nullptr; // the same, FP64-state prox
+  // stored Cholesky factors of the weight prox (factor reuse), allocated on demand
+  int64_t fac_B = 0;
+  double *Lg = nullptr, *wH = nullptr;
+  unsigned long long* maskH = nullptr;
+  int* validH = nullptr;
   int* mm_until = nullptr;  // last iteration of each spectrum's MM warm-up (exact weight prox)
   int* xflags = nullptr;    // status bits set on the way: 16 warm start replaced, 32 range promotion
   int* it_base = nullptr;   // per-spectrum offset of refinement-phase iteration indices
@@ -73,6 +80,8 @@ struct Workspace {
   void release() {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
+    for (void* q : {(void*)Lg, (void*)wH, (void*)maskH, (void*)validH})
+      if (q) (void)hipFree(q);
     if (host_flags) (void)hipHostFree(host_flags);
     host_flags = nullptr;
     B = np = kp = 0;
@@ -82,7 +91,11 @@ struct Workspace {
     ew_prev = nullptr;
     ew_best = nullptr;
     stall = nullptr;
-    nit = nit64 = nullptr;
+    nit = nit64 = nfac = nfac64 = nullptr;
+    fac_B = 0;
+    Lg = wH = nullptr;
+    maskH = nullptr;
+    validH = nullptr;
     mm_until = xflags = it_base = nullptr;
     Vbf = Ubf = nullptr;
   }
@@ -105,6 +118,12 @@ struct Workspace {
 // cold start s = K 1 carries far more mass than y and an exact prox there
 // drives weights to scales that Newton leaves only slowly.
 constexpr int OTLM_MM_WARMUP = 3;
+// A Newton iteration of the weight prox reuses the spectrum's last Cholesky
+// factor while the free set is unchanged and the weights moved by at most this
+// fraction of max|w| since it was built (0: always refactor).
+#ifndef OTLM_HESS_REUSE
+#define OTLM_HESS_REUSE 1e-2
+#endif
 // Scaled gradient tolerance of the Newton weight prox during an FP32 bulk phase
 // that an FP64 refinement will follow (the outer iterate is itself only good to
 // ~1e-5 there); the FP64 phase and FP32-only solves use 1e-13.
@@ -142,7 +161,7 @@ struct otlm_kernel_s {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double prof_ms[OTLM_PROF_CLASSES] = {};
   int64_t prof_n[OTLM_PROF_CLASSES] = {};
-  int64_t prof_newton[2] = {0, 0};  // Newton iterations of the weight prox, FP32 / FP64 state (summed over spectra)
+  int64_t prof_newton[4] = {0, 0, 0, 0};  // weight prox: Newton iterations FP32 / FP64 state, then factorisations
 };
 
 namespace {
@@ -186,6 +205,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.stall, (size_t)B);
   rc |= dev_alloc(ws, &ws.nit, (size_t)B);
   rc |= dev_alloc(ws, &ws.nit64, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nfac, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nfac64, (size_t)B);
   rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
   rc |= dev_alloc(ws, &ws.xflags, (size_t)B);
   rc |= dev_alloc(ws, &ws.it_base, (size_t)B);
@@ -395,7 +416,7 @@ int otlm_profile_enable(otlm_kernel k, int32_t on) {
     k->prof_ms[c] = 0.0;
     k->prof_n[c] = 0;
   }
-  k->prof_newton[0] = k->prof_newton[1] = 0;
+  for (int q = 0; q < 4; ++q) k->prof_newton[q] = 0;
   k->profile = on != 0;
   return OTLM_OK;
 }
@@ -403,10 +424,8 @@ int otlm_profile_enable(otlm_kernel k, int32_t on) {
 int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton_iters) {
   if (!k) return OTLM_E_INVALID;
   prof_collect(k);
-  if (newton_iters) {
-    newton_iters[0] = k->prof_newton[0];
-    newton_iters[1] = k->prof_newton[1];
-  }
+  if (newton_iters)
+    for (int q = 0; q < 4; ++q) newton_iters[q] = k->prof_newton[q];
   for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     if (ms) ms[c] = k->prof_n[c] ? k->prof_ms[c] / (double)k->prof_n[c] : 0.0;
     if (count) count[c] = k->prof_n[c];
@@ -481,9 +500,30 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
 
   OTLM_HIP(hipMemsetAsync(ws.flags, 0, 4 * sizeof(int), s));
+  bool reuse = false;
   if (exact) {
     OTLM_HIP(hipMemsetAsync(ws.nit, 0, (size_t)B * sizeof(int), s));
     OTLM_HIP(hipMemsetAsync(ws.nit64, 0, (size_t)B * sizeof(int), s));
+    OTLM_HIP(hipMemsetAsync(ws.nfac, 0, (size_t)B * sizeof(int), s));
+    OTLM_HIP(hipMemsetAsync(ws.nfac64, 0, (size_t)B * sizeof(int), s));
+    if (OTLM_HESS_REUSE > 0.0 && ws.fac_B < B) {  // factor storage: 32 KB per spectrum; without it, no reuse
+      for (void* q : {(void*)ws.Lg, (void*)ws.wH, (void*)ws.maskH, (void*)ws.validH})
+        if (q) (void)hipFree(q);
+      ws.Lg = ws.wH = nullptr;
+      ws.maskH = nullptr;
+      ws.validH = nullptr;
+      ws.fac_B = 0;
+      if (hipMalloc(&ws.Lg, (size_t)B * PN_K * PN_K * sizeof(double)) == hipSuccess &&
+          hipMalloc(&ws.wH, (size_t)B * PN_K * sizeof(double)) == hipSuccess &&
+          hipMalloc(&ws.maskH, (size_t)B * sizeof(unsigned long long)) == hipSuccess &&
+          hipMalloc(&ws.validH, (size_t)B * sizeof(int)) == hipSuccess) {
+        ws.fac_B = B;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    reuse = OTLM_HESS_REUSE > 0.0 && ws.fac_B >= B;
+    if (reuse) OTLM_HIP(hipMemsetAsync(ws.validH, 0, (size_t)B * sizeof(int), s));
   }
   OTLM_HIP(hipMemsetAsync(ws.it_base, 0, (size_t)B * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
@@ -525,6 +565,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<float, float> a;
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = ws.mm_until; a.it = 0;
+    a.nfac = ws.nfac; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.reuse_tol = OTLM_HESS_REUSE;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
     a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
@@ -535,6 +577,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<double, double> a;
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = nullptr; a.it = 0;
+    a.nfac = ws.nfac64; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.reuse_tol = OTLM_HESS_REUSE;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit64;
@@ -726,12 +770,16 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   OTLM_HIP(hipGetLastError());
   if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
     std::vector<int> h((size_t)B);
-    std::vector<int> h64((size_t)B);
+    std::vector<int> h64((size_t)B), f32((size_t)B), f64((size_t)B);
     OTLM_HIP(hipMemcpyAsync(h.data(), ws.nit, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipMemcpyAsync(h64.data(), ws.nit64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipMemcpyAsync(f32.data(), ws.nfac, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipMemcpyAsync(f64.data(), ws.nfac64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipStreamSynchronize(s));
     for (int v : h) k->prof_newton[0] += v;
     for (int v : h64) k->prof_newton[1] += v;
+    for (int v : f32) k->prof_newton[2] += v;
+    for (int v : f64) k->prof_newton[3] += v;
   }
   return OTLM_OK;
 }

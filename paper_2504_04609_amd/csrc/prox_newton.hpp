@@ -24,6 +24,15 @@
 // 8 x 4 register blocks per thread over two bin groups; the Cholesky
 // factorisation runs by 16 x 16 tiles and the two triangular solves in one wave,
 // one row per lane.
+//
+// Factor reuse: the Hessian depends on the weights only (through a = D w), not
+// on s, so a Cholesky factor stays accurate while w barely moves, as it does
+// between late outer iterations.  Each spectrum keeps its last factor, the
+// weights it was built at and its free set in global memory; a Newton
+// iteration reuses it (a chord step, still safeguarded by the ratio test and
+// Armijo) when the free set is the same and max|w - w_H| <= reuse_tol max|w_H|
+// and the previous step, if it reused the factor, at least halved the free-set
+// gradient; otherwise it builds and factors the Hessian anew.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "solver_kernels.hpp"
@@ -43,7 +52,13 @@ struct ProxNewtonArgs {
   const int* done;
   const int* mm_until;  // spectra with it <= mm_until[b] take the MM step instead (null: none)
   int it;
-  int* nit;            // Newton iterations done, accumulated per spectrum
+  int* nit;
+  int* nfac;                   // Hessian factorisations, accumulated per spectrum
+  double* Lg;                  // [B][64 * 64] last Cholesky factor per spectrum (null: no reuse)
+  double* wH;                  // [B][64] weights at that factorisation
+  unsigned long long* maskH;   // [B] its active set (bit j: w_j pinned at 0)
+  int* validH;                 // [B] 1 when the stored factor may be used
+  double reuse_tol;            // Newton iterations done, accumulated per spectrum
   int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
 };
@@ -152,6 +167,16 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   TS* s = reinterpret_cast<TS*>(red + 8);  // [n]
   __shared__ int act[PN_K];
   __shared__ int ctl[4];
+  __shared__ double wHs[PN_K];            // weights of the factor held in H
+  __shared__ unsigned long long hmask_s;  // its active set
+  __shared__ int hstate[2];               // [0] H holds a usable factor, [1] it was rebuilt here
+  __shared__ double hrel_diag_s;          // Hessian diagonal entry of a released weight
+  __shared__ double kkt_s;                // free-set gradient of this iteration
+  double kkt_prev = 0.0;                  // (thread 0) that of the previous iteration
+  int last_reused = 0;                    // (thread 0) the previous step used a reused factor
+  __shared__ int force_rebuild;           // the last reused factor gave no descent
+  if (threadIdx.x == 0) force_rebuild = 0;
+  int nfac = 0;
 
   const TS* srow = p.S + (size_t)b * p.ld_s;
   TW* wrow = p.W + (size_t)b * p.ld_w;
@@ -160,6 +185,18 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     const double wj = j < k ? (double)wrow[j] : 0.0;
     w[j] = wj > 0.0 ? wj : 0.0;
     act[j] = (j < k && wj > 0.0) ? 0 : 1;   // padded columns stay active at 0
+  }
+  const bool reuse_on = p.Lg && p.reuse_tol > 0.0;
+  if (tid == 0) {
+    hstate[0] = reuse_on && p.validH[b];
+    hstate[1] = 0;
+    hmask_s = reuse_on ? p.maskH[b] : 0ull;
+  }
+  __syncthreads();
+  if (hstate[0]) {  // the factor of the previous launch
+    const double* Lb = p.Lg + (size_t)b * PN_K * PN_K;
+    for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) H[(e >> 6) * PN_HLD + (e & 63)] = Lb[e];
+    if (tid < PN_K) wHs[tid] = p.wH[(size_t)b * PN_K + tid];
   }
   __syncthreads();
   const double tiny = 1e-300;
@@ -217,10 +254,34 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       ctl[0] = stop;
       ctl[1] = released;
       ctl[2] = (jmin >= 0 && gmin < -gscale) ? jmin : -1;   // release candidate if no descent is left
+      kkt_s = kkt;
     }
     __syncthreads();
     if (ctl[0]) break;
     const int released = ctl[1];
+    if (tid == 0) {  // reuse the factor held in H?
+      unsigned long long mask = 0ull;
+      for (int j = 0; j < k; ++j)
+        if (act[j]) mask |= 1ull << j;
+      int reuse = 0;
+      // a step on a reused factor that did not halve the free gradient: refactor
+      const bool poor = (last_reused && kkt_s > 0.5 * kkt_prev) || force_rebuild;
+      force_rebuild = 0;
+      if (hstate[0] && released < 0 && mask == hmask_s && !poor) {
+        double dm = 0.0, wm = 0.0;
+        for (int j = 0; j < k; ++j) {
+          dm = fmax(dm, fabs(w[j] - wHs[j]));
+          wm = fmax(wm, fabs(wHs[j]));
+        }
+        reuse = dm <= p.reuse_tol * wm;
+      }
+      ctl[3] = reuse;
+      if (!reuse) hmask_s = mask;
+      last_reused = reuse;
+      kkt_prev = kkt_s;
+    }
+    __syncthreads();
+    if (!ctl[3]) {
 
     // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
     for (int i = tid; i < n; i += PN_THREADS) l[i] = 1.0 / fmax(a[i], tiny);
@@ -271,7 +332,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       H[r * PN_HLD + c] = h;
     }
     __syncthreads();
-    const double hrel_diag = released >= 0 ? H[released * PN_HLD + released] : 1.0;
+    if (tid == 0) hrel_diag_s = released >= 0 ? H[released * PN_HLD + released] : 1.0;
     __syncthreads();
 
     // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
@@ -323,10 +384,20 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       __syncthreads();
     }
 
+      if (tid < PN_K) wHs[tid] = w[tid];
+      if (tid == 0) {
+        hstate[0] = 1;
+        hstate[1] = 1;
+      }
+      ++nfac;
+      __syncthreads();
+    }
+    const double hrel_diag_used = released >= 0 ? hrel_diag_s : 1.0;
+
     // ---- solve L L^T d = -g in wave 0 (lane r owns row r)
     if (wave == 0) {
       const int r = lane;
-      const double hdiag_released = released >= 0 ? hrel_diag : 1.0;
+      const double hdiag_released = hrel_diag_used;
       const double* Hr = H + r * PN_HLD;
       // forward: L y = -g ; backward: L^T d = y   (active rows: g = 0, L row = e_r)
       double y = act[r] ? 0.0 : -g[r];
@@ -377,6 +448,12 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
         t *= 0.5;
       }
     }
+    if (!accepted && ctl[3]) {  // the step on a reused factor failed: retry with a fresh factor
+      __syncthreads();
+      if (tid == 0) force_rebuild = 1;
+      __syncthreads();
+      continue;
+    }
     if (!accepted) {  // no descent left on this free set: release the candidate, or stop
       const int cand = ctl[2];
       __syncthreads();
@@ -400,10 +477,22 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     __syncthreads();
   }
 
-  // ---- write back
+  // ---- write back (and the last factor, for the next launch)
   if (tid < k) wrow[tid] = (TW)w[tid];
   if (tid < PN_K && tid >= k && tid < p.ld_w) wrow[tid] = (TW)0;
-  if (tid == 0) p.nit[b] += it;
+  if (tid == 0) {
+    p.nit[b] += it;
+    if (p.nfac) p.nfac[b] += nfac;
+  }
+  if (reuse_on && hstate[1]) {
+    double* Lb = p.Lg + (size_t)b * PN_K * PN_K;
+    for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) Lb[e] = H[(e >> 6) * PN_HLD + (e & 63)];
+    if (tid < PN_K) p.wH[(size_t)b * PN_K + tid] = wHs[tid];
+    if (tid == 0) {
+      p.maskH[b] = hmask_s;
+      p.validH[b] = 1;
+    }
+  }
 }
 
 inline size_t prox_newton_smem(int n, size_t s_bytes) {
