@@ -241,7 +241,10 @@ int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton
  * fused workgroup per spectrum.  The weight step is the MM step of Table 2,
  * taken p->inner_max times per outer iteration at the same s = K v (every
  * repetition majorizes the same ProxP problem, so the limit is the one of
- * the single step; more repetitions cut the number of kernel products).
+ * the single step; more repetitions cut the number of kernel products), and
+ * for the spectra still active after opts->newton_after iterations the exact
+ * weight prox (ProxP minimised by active-set Newton): MM steps crawl where
+ * small weights sit under large overlapping peaks.
  * FP32 state and products (OTLM_PREC_FP32, OTLM_WSTEP_MM, no refinement).
  *
  * Packed arrays (device, FP32, in input order b = 0..B-1, no padding):
@@ -260,10 +263,14 @@ typedef struct {
                           grouped kernel products (128x128, 128x64, 64x128,
                           64x64) on the plan's own shapes at create and keep
                           the fastest; 0..3: use that shape                  */
-  int32_t reserved[2]; /* set to 0                                            */
+  int32_t newton_after;/* 60 (default): a spectrum with kdim <= 64 and n <= 2048
+                          still active after this many iterations takes the
+                          exact weight prox (active-set Newton, as
+                          OTLM_WSTEP_EXACT) instead of MM steps; -1: MM only  */
+  int32_t reserved;    /* set to 0                                            */
 } otlm_ragged_opts;
 
-/* use_graph = 1, tile = -1. */
+/* use_graph = 1, tile = -1, newton_after = 60. */
 void otlm_ragged_default_opts(otlm_ragged_opts* o);
 
 /* Plan a ragged solve.
@@ -301,9 +308,10 @@ int otlm_ragged_solve(otlm_ragged r, const float* D, const float* Y, float* W, f
  * sum n_b kdim[b], device bytes held by the plan}.  Any output may be NULL. */
 int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* tune_ms, int64_t* sizes);
 
-/* Kernel timing of ragged solves, as otlm_profile_*, with 4 classes:
+/* Kernel timing of ragged solves, as otlm_profile_*, with 5 classes:
  * [0] grouped s = K v products  [1] per-spectrum weight step  [2] grouped
- * t = K^T u products with the target prox  [3] convergence test.  While
+ * t = K^T u products with the target prox  [3] convergence test
+ * [4] Newton weight prox.  While
  * enabled the solve launches eagerly (no graph replay) and counts the
  * algorithmic work of the timed launches into work[2] (may be NULL):
  * [0] multiply-adds of the kernel products, sum over launches and active

@@ -567,6 +567,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.mm_until = ws.mm_until; a.it = 0;
     a.nfac = ws.nfac; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
+    a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
     a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
@@ -579,6 +580,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.mm_until = nullptr; a.it = 0;
     a.nfac = ws.nfac64; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
+    a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit64;
@@ -606,7 +608,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
     if (exact) {  // weight prox solved by active-set Newton (spectra past their MM warm-up)
       ProfScope ps(k, PROF_W32, s);
-      auto kern = prox_newton_kernel<float, float>;
+      auto kern = prox_newton_kernel<float, float, double, PN_MAXB>;
       auto a = prox_args32();
       a.it = it;
       hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS), prox_newton_smem((int)n, sizeof(float)), s, a);
@@ -649,7 +651,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
     {
       ProfScope ps(k, PROF_W64, s);
-      auto kern = prox_newton_kernel<double, double>;
+      auto kern = prox_newton_kernel<double, double, double, PN_MAXB>;
       hipLaunchKernelGGL(kern, dim3((unsigned)B), dim3(PN_THREADS),
                          prox_newton_smem((int)n, sizeof(double)), s, prox_args64());
     }

@@ -40,7 +40,18 @@
 constexpr int PN_THREADS = 256;
 constexpr int PN_K = 64;    // largest dictionary handled by this kernel
 constexpr int PN_HLD = PN_K + 1;
-constexpr int PN_MAXB = 4;  // bins per thread in bin sweeps: n <= 1024
+constexpr int PN_MAXB = 4;  // bins per thread in bin sweeps of a batch: n <= 1024
+constexpr int PN_MAXB_RAGGED = 8;  // the same for ragged batches: n <= 2048
+
+// Per-spectrum layout of a ragged batch (ProxNewtonArgs::rg; null for a batch
+// that shares one dictionary and the strides of the arguments).
+struct PnSpec {
+  long long s_off;   // start of s_b in S
+  long long w_off;   // start of w_b in W (packed, k_b entries)
+  long long dp_off;  // start of D_b in Dp: [n_b, 64] row-major, columns >= k_b zero
+  long long dt_off;  // start of D_b^T in DTp: [k_b, n_b]
+  int n, k;
+};
 
 template <class TS, class TW>
 struct ProxNewtonArgs {
@@ -58,7 +69,10 @@ struct ProxNewtonArgs {
   double* wH;                  // [B][64] weights at that factorisation
   unsigned long long* maskH;   // [B] its active set (bit j: w_j pinned at 0)
   int* validH;                 // [B] 1 when the stored factor may be used
-  double reuse_tol;            // Newton iterations done, accumulated per spectrum
+  double reuse_tol;
+  const PnSpec* rg;            // ragged layout (null: batch layout)
+  const int* it_dev;           // ragged: the iteration counter ...
+  int newton_after;            // ... spectra take the prox once it exceeds this
   int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
   double eps, alpha, beta, gtol;
 };
@@ -104,41 +118,41 @@ __device__ __forceinline__ double pn_pen_grad(int pen, double w, double alpha, d
 // V(w) = eps sum_i (a_i log(a_i/s_i) - a_i + s_i) + sum_j alpha R(w_j), a = D w
 // (bins with a = 0 give s_i); stores a when `a` is not null.  Each thread owns
 // up to PN_MAXB bins and keeps their sums independent so the D^T loads overlap.
-template <class TS, class TW>
-__device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const double* w, const TS* s, double* a, double* red) {
-  const int n = p.n, k = p.k;
-  double ai[PN_MAXB];
+template <int MAXB, class TS, class TW, class TL>
+__device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int ld_dt, int n, int k,
+                          const double* w, const TS* s, TL* a, double* red) {
+  double ai[MAXB];
 #pragma unroll
-  for (int q = 0; q < PN_MAXB; ++q) ai[q] = 0.0;
-  const float* base = p.DTp + threadIdx.x;
+  for (int q = 0; q < MAXB; ++q) ai[q] = 0.0;
+  const float* base = DTp + threadIdx.x;
   const int nq = (n - (int)threadIdx.x + PN_THREADS - 1) / PN_THREADS;  // bins of this thread
   int j = 0;
   for (; j + 7 < k; j += 8) {  // eight columns per step: up to 32 independent loads in flight
-    float dv[8][PN_MAXB];
+    float dv[8][MAXB];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int q = 0; q < PN_MAXB; ++q)
-        dv[u][q] = q < nq ? base[(size_t)(j + u) * p.ld_dt + q * PN_THREADS] : 0.f;
+      for (int q = 0; q < MAXB; ++q)
+        dv[u][q] = q < nq ? base[(size_t)(j + u) * ld_dt + q * PN_THREADS] : 0.f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double wj = w[j + u];
 #pragma unroll
-      for (int q = 0; q < PN_MAXB; ++q) ai[q] += (double)dv[u][q] * wj;
+      for (int q = 0; q < MAXB; ++q) ai[q] += (double)dv[u][q] * wj;
     }
   }
   for (; j < k; ++j) {
     const double wj = w[j];
 #pragma unroll
-    for (int q = 0; q < PN_MAXB; ++q)
-      if (q < nq) ai[q] += (double)base[(size_t)j * p.ld_dt + q * PN_THREADS] * wj;
+    for (int q = 0; q < MAXB; ++q)
+      if (q < nq) ai[q] += (double)base[(size_t)j * ld_dt + q * PN_THREADS] * wj;
   }
   double acc = 0.0;
 #pragma unroll
-  for (int q = 0; q < PN_MAXB; ++q) {
+  for (int q = 0; q < MAXB; ++q) {
     const int i = threadIdx.x + q * PN_THREADS;
     if (i < n) {
-      if (a) a[i] = ai[q];
+      if (a) a[i] = (TL)ai[q];
       const double si = (double)s[i];
       acc += (ai[q] > 0.0 ? ai[q] * log(ai[q] / si) : 0.0) - ai[q] + si;
     }
@@ -149,22 +163,42 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const double* w, cons
   return v + pv;
 }
 
-template <class TS, class TW>
+// MAXB: bins per thread (n <= 256 MAXB); TL: storage of a and of log(a/s) or
+// 1/a in LDS (double for a batch, float for the n <= 2048 of a ragged batch).
+template <class TS, class TW, class TL, int MAXB>
 __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<TS, TW> p) {
   const int b = blockIdx.x;
   if (p.done[b] || (p.mm_until && p.it <= p.mm_until[b])) return;
+  int n = p.n, k = p.k, ld_d = p.ld_d, ld_dt = p.ld_dt, ld_w = p.ld_w;
+  const float* Dp = p.Dp;
+  const float* DTp = p.DTp;
+  const TS* srow = p.S + (size_t)b * p.ld_s;
+  TW* wrow = p.W + (size_t)b * p.ld_w;
+  if (p.rg) {  // ragged: this spectrum's own sizes and arrays, once it is past its MM iterations
+    const PnSpec sp = p.rg[b];
+    if (sp.dp_off < 0 || p.it_dev[0] <= p.newton_after) return;
+    n = sp.n;
+    k = sp.k;
+    ld_d = PN_K;
+    ld_dt = sp.n;
+    ld_w = sp.k;
+    Dp = p.Dp + sp.dp_off;
+    DTp = p.DTp + sp.dt_off;
+    srow = p.S + sp.s_off;
+    wrow = p.W + sp.w_off;
+  }
   extern __shared__ double smem[];
-  const int n = p.n, k = p.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* a = smem;                    // [n]  D w at the current point
-  double* l = a + n;                   // [n]  log(a/s) or 1/sqrt(a)
-  double* H = l + n;                   // [64][65]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* H = smem;                    // [64][65]
   double* w = H + PN_K * PN_HLD;       // [64]
   double* wt = w + PN_K;               // [64]
   double* g = wt + PN_K;               // [64]
   double* d = g + PN_K;                // [64]
   double* gp = d + PN_K;               // [4][64] gradient partials
   double* red = gp + 4 * PN_K;         // [8]
-  TS* s = reinterpret_cast<TS*>(red + 8);  // [n]
+  TL* a = reinterpret_cast<TL*>(red + 8);  // [n]  D w at the current point
+  TL* l = a + n;                       // [n]  log(a/s) or 1/a
+  TS* s = reinterpret_cast<TS*>(l + n);  // [n]
   __shared__ int act[PN_K];
   __shared__ int ctl[4];
   __shared__ double wHs[PN_K];            // weights of the factor held in H
@@ -178,8 +212,6 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   if (threadIdx.x == 0) force_rebuild = 0;
   int nfac = 0;
 
-  const TS* srow = p.S + (size_t)b * p.ld_s;
-  TW* wrow = p.W + (size_t)b * p.ld_w;
   for (int i = tid; i < n; i += PN_THREADS) s[i] = srow[i];
   for (int j = tid; j < PN_K; j += PN_THREADS) {
     const double wj = j < k ? (double)wrow[j] : 0.0;
@@ -199,15 +231,15 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     if (tid < PN_K) wHs[tid] = p.wH[(size_t)b * PN_K + tid];
   }
   __syncthreads();
-  const double tiny = 1e-300;
+  const double tiny = sizeof(TL) == 4 ? 1e-30 : 1e-300;
   const double gscale = fmax(fmax(p.alpha, p.eps), 1e-300) * p.gtol;
   const double hpen = p.pen == PEN_L2SQ ? p.alpha : (p.pen == PEN_EN ? p.beta : 0.0);
 
   int it = 0;
   for (; it < p.max_newton; ++it) {
-    const double f = pn_eval(p, w, s, a, red);   // also a = D w (block_sum synchronises)
+    const double f = pn_eval<MAXB>(p, DTp, ld_dt, n, k, w, s, a, red);  // also a = D w (block_sum synchronises)
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
-    for (int i = tid; i < n; i += PN_THREADS) l[i] = log(fmax(a[i], tiny) / (double)s[i]);
+    for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)log(fmax((double)a[i], tiny) / (double)s[i]);
     __syncthreads();
     {
       // thread (j = lane, q = wave) sums bins i = q, q + 4, ... of column j;
@@ -217,13 +249,13 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
 #pragma unroll
       for (int u = 0; u < 8; ++u) part[u] = 0.0;
       if (j < k) {
-        const float* dcol = p.Dp + j;
+        const float* dcol = Dp + j;
         int i = q;
         for (; i + 28 < n; i += 32) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * p.ld_d] * l[i + 4 * u];
+          for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * ld_d] * (double)l[i + 4 * u];
         }
-        for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * p.ld_d] * l[i];
+        for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * ld_d] * (double)l[i];
       }
       gp[q * PN_K + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
       __syncthreads();
@@ -284,7 +316,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     if (!ctl[3]) {
 
     // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
-    for (int i = tid; i < n; i += PN_THREADS) l[i] = 1.0 / fmax(a[i], tiny);
+    for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)(1.0 / fmax((double)a[i], tiny));
     __syncthreads();
     {
       // 128 register blocks of 8 x 4 entries (block row bj = 0..7, block column
@@ -295,12 +327,12 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       for (int x = 0; x < 8; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      const float* rowj = p.Dp + bj * 8;
-      const float* rowl = p.Dp + bl * 4;
+      const float* rowj = Dp + bj * 8;
+      const float* rowl = Dp + bl * 4;
       for (int i = q; i < n; i += 2) {
-        const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * p.ld_d);
-        const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * p.ld_d + 4);
-        const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * p.ld_d);
+        const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
+        const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
+        const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
         const double sc = l[i];  // 1 / a_i
         const double xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
         const double xb[4] = {(double)lv.x, (double)lv.y, (double)lv.z, (double)lv.w};
@@ -440,7 +472,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       for (int ls = 0; ls < 30; ++ls) {
         if (tid < PN_K) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
         __syncthreads();
-        const double fn = pn_eval(p, wt, s, nullptr, red);
+        const double fn = pn_eval<MAXB>(p, DTp, ld_dt, n, k, wt, s, (TL*)nullptr, red);
         if (fn <= f + 1e-4 * t * slope) {
           accepted = true;
           break;
@@ -479,7 +511,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
 
   // ---- write back (and the last factor, for the next launch)
   if (tid < k) wrow[tid] = (TW)w[tid];
-  if (tid < PN_K && tid >= k && tid < p.ld_w) wrow[tid] = (TW)0;
+  if (tid < PN_K && tid >= k && tid < ld_w) wrow[tid] = (TW)0;
   if (tid == 0) {
     p.nit[b] += it;
     if (p.nfac) p.nfac[b] += nfac;
@@ -495,6 +527,6 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   }
 }
 
-inline size_t prox_newton_smem(int n, size_t s_bytes) {
-  return sizeof(double) * ((size_t)2 * n + PN_K * PN_HLD + 8 * PN_K + 8) + s_bytes * (size_t)n;
+inline size_t prox_newton_smem(int n, size_t s_bytes, size_t l_bytes = sizeof(double)) {
+  return sizeof(double) * ((size_t)PN_K * PN_HLD + 8 * PN_K + 8) + (2 * l_bytes + s_bytes) * (size_t)n;
 }

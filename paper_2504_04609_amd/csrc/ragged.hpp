@@ -15,7 +15,11 @@
 namespace {
 
 constexpr int RG_TILES[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
-enum { RG_PROF_KV = 0, RG_PROF_W, RG_PROF_KTU, RG_PROF_CHECK, RG_PROF_CLASSES };
+enum { RG_PROF_KV = 0, RG_PROF_W, RG_PROF_KTU, RG_PROF_CHECK, RG_PROF_NEWTON, RG_PROF_CLASSES };
+// Newton prox of the ragged path: inner iterations per launch and scaled
+// gradient tolerance (FP32 state, a and log(a/s) held in FP32).
+constexpr int RG_NEWTON_MAX = 5;
+constexpr double RG_NEWTON_GTOL = 1e-7;
 
 }  // namespace
 
@@ -39,6 +43,15 @@ struct otlm_ragged_s {
   float* Wsnap = nullptr;  // weights at the previous convergence test
   GemmActive* act = nullptr;  // active rows of the grouped products (device)
   int* nband = nullptr;       // band entries of each spectrum's dictionary
+  // Newton prox of the spectra still active after newton_after iterations (k <= 64, n <= 2048)
+  int newton_after = -1;
+  int n_newton = 0, nmax_newton = 0;  // spectra that may take it, their largest n
+  int64_t tot_dp = 0;
+  float* Dp = nullptr;
+  PnSpec* pnspec = nullptr;
+  double *Lg = nullptr, *wH = nullptr;
+  unsigned long long* maskH = nullptr;
+  int *validH = nullptr, *nit = nullptr, *nfac = nullptr;
   unsigned long long* work = nullptr;  // profiling: [0] kernel-product MACs, [1] weight-step bytes
   int* act_rows = nullptr;
   RgGroups gi{};
@@ -201,11 +214,25 @@ void rg_iterate(otlm_ragged_s* r, bool chk, hipStream_t s) {
     RgProfScope ps(r, RG_PROF_KV, s);
     rg_product_s(r, r->tile, chk, s);
   }
+  if (r->n_newton > 0) {
+    RgProfScope ps(r, RG_PROF_NEWTON, s);
+    ProxNewtonArgs<float, float> a{};
+    a.S = r->S; a.W = r->Wst; a.Dp = r->Dp; a.DTp = r->DT; a.colc = r->colc; a.done = r->done;
+    a.mm_until = nullptr; a.it = 0; a.nit = r->nit; a.nfac = r->nfac;
+    a.Lg = r->Lg; a.wH = r->wH; a.maskH = r->maskH; a.validH = r->validH; a.reuse_tol = OTLM_HESS_REUSE;
+    a.rg = r->pnspec; a.it_dev = r->it_dev; a.newton_after = r->newton_after;
+    a.pen = r->p.pen; a.max_newton = RG_NEWTON_MAX; a.eps = r->p.eps; a.alpha = r->p.alpha; a.beta = r->p.beta;
+    a.gtol = RG_NEWTON_GTOL;
+    auto kern = prox_newton_kernel<float, float, float, PN_MAXB_RAGGED>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)r->B), dim3(PN_THREADS),
+                       prox_newton_smem(r->nmax_newton, sizeof(float), sizeof(float)), s, a);
+  }
   {
     RgProfScope ps(r, RG_PROF_W, s);
-    hipLaunchKernelGGL(rg_weight_step, dim3((unsigned)r->B), dim3(RG_THREADS), 3 * (size_t)r->npmax * sizeof(float),
+    hipLaunchKernelGGL(rg_weight_step, dim3((unsigned)r->B), dim3(RG_WS_THREADS), 3 * (size_t)r->npmax * sizeof(float),
                        s, r->spec, r->DT, r->colc, r->band, r->p.pen, r->p.inner_max, r->S, r->A, r->U, r->Wst,
-                       r->done, (const int*)r->nband, r->profile ? r->work + 1 : nullptr);
+                       r->done, (const int*)r->nband, r->profile ? r->work + 1 : nullptr, (const int*)r->it_dev,
+                       r->n_newton > 0 ? r->newton_after : -1);
   }
   {
     RgProfScope ps(r, RG_PROF_KTU, s);
@@ -296,6 +323,7 @@ void otlm_ragged_default_opts(otlm_ragged_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->use_graph = 1;
   o->tile = -1;
+  o->newton_after = 60;
 }
 
 int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32_t* kernel_of, const int32_t* kdim,
@@ -308,7 +336,7 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
   otlm_ragged_opts o;
   otlm_ragged_default_opts(&o);
   if (opts) o = *opts;
-  if (o.tile < -1 || o.tile > 3) return OTLM_E_INVALID;
+  if (o.tile < -1 || o.tile > 3 || o.newton_after < -1) return OTLM_E_INVALID;
   for (int g = 0; g < nkernels; ++g) {
     if (!kernels[g] || !params_valid(p, kernels[g]->eps)) return OTLM_E_INVALID;
     if (kernels[g]->n > RG_MAX_N) return OTLM_E_UNSUPPORTED;
@@ -333,6 +361,7 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
   r->B = B;
   r->p = *p;
   r->use_graph = o.use_graph != 0;
+  r->newton_after = o.newton_after;
   r->pc.fit = p->fit;
   r->pc.kappa = (float)(p->lambda / (p->lambda + p->eps));
   r->pc.lam_eps = (float)(p->lambda / p->eps);
@@ -385,7 +414,7 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
   for (int64_t b = 0; b < B; ++b) q_of[b] = next_row[group_of_kernel[kernel_of[b]]]++;
   std::vector<int64_t> b_of(B);
   for (int64_t b = 0; b < B; ++b) b_of[q_of[b]] = b;
-  int64_t odt = 0, ocol = 0;
+  int64_t odt = 0, ocol = 0, odp = 0;
   for (int64_t q = 0; q < B; ++q) {
     const int64_t b = b_of[q];
     const int g = group_of_kernel[kernel_of[b]];
@@ -403,6 +432,19 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
     sp.win = win[b];
     odt += (int64_t)G.n * kdim[b];
     ocol += kdim[b];
+    sp.dp = -1;
+    if (r->newton_after >= 0 && sp.k <= PN_K && sp.n <= PN_THREADS * PN_MAXB_RAGGED) {
+      sp.dp = odp;
+      odp += (int64_t)sp.n * PN_K;
+      r->n_newton += 1;
+      r->nmax_newton = std::max(r->nmax_newton, sp.n);
+    }
+  }
+  r->tot_dp = odp;
+  std::vector<PnSpec> hpn(B);
+  for (int64_t q = 0; q < B; ++q) {
+    const RgSpec& sp = r->hspec[q];
+    hpn[q] = PnSpec{sp.st, sp.col, sp.dp, sp.dt, sp.n, sp.k};
   }
 
   bool ok = r->alloc(&r->spec, B) && r->alloc(&r->V, r->tot_state) && r->alloc(&r->S, r->tot_state) &&
@@ -412,11 +454,17 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
             r->alloc(&r->pwn, B) && r->alloc(&r->pwd, B) && r->alloc(&r->ew_prev, B) && r->alloc(&r->ew_best, B) &&
             r->alloc(&r->done, B) && r->alloc(&r->iters, B) && r->alloc(&r->status, B) && r->alloc(&r->flags, 4) &&
             r->alloc(&r->stall, B) && r->alloc(&r->it_dev, 1) && r->alloc(&r->act, 1) &&
-            r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 2);
+            r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 2) &&
+            r->alloc(&r->Dp, r->tot_dp) && r->alloc(&r->pnspec, B) && r->alloc(&r->nit, B) &&
+            r->alloc(&r->nfac, B) && r->alloc(&r->validH, B) && r->alloc(&r->maskH, B) &&
+            r->alloc(&r->wH, r->n_newton ? B * PN_K : 1) && r->alloc(&r->Lg, r->n_newton ? B * PN_K * PN_K : 1);
   if (!ok) return fail(OTLM_E_NOMEM);
   if (hipHostMalloc((void**)&r->host_flags, 4 * sizeof(int)) != hipSuccess) return fail(OTLM_E_NOMEM);
   const size_t sb = (size_t)r->tot_state * sizeof(float);
   if (hipMemcpyAsync(r->spec, r->hspec.data(), (size_t)B * sizeof(RgSpec), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(r->pnspec, hpn.data(), (size_t)B * sizeof(PnSpec), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(r->nit, 0, (size_t)B * sizeof(int), s) != hipSuccess ||
+      hipMemsetAsync(r->nfac, 0, (size_t)B * sizeof(int), s) != hipSuccess ||
       hipMemsetAsync(r->V, 0, sb, s) != hipSuccess || hipMemsetAsync(r->A, 0, sb, s) != hipSuccess ||
       hipMemsetAsync(r->U, 0, sb, s) != hipSuccess || hipMemsetAsync(r->done, 0, (size_t)B * sizeof(int), s) != hipSuccess)
     return fail(OTLM_E_HIP);
@@ -445,7 +493,8 @@ int otlm_ragged_solve(otlm_ragged r, const float* D, const float* Y, float* W, f
   OTLM_HIP(hipMemsetAsync(r->flags, 0, 4 * sizeof(int), s));
   OTLM_HIP(hipMemsetAsync(r->it_dev, 0, sizeof(int), s));
   hipLaunchKernelGGL(rg_prep_dict, dim3((unsigned)r->B), dim3(RG_THREADS), 0, s, r->spec, D, p.pen, p.eps, p.alpha,
-                     p.beta, r->DT, r->colc, r->band, r->nband, r->flags + 1);
+                     p.beta, r->DT, r->Dp, r->colc, r->band, r->nband, r->flags + 1);
+  OTLM_HIP(hipMemsetAsync(r->validH, 0, (size_t)r->B * sizeof(int), s));
   hipLaunchKernelGGL(rg_init, dim3((unsigned)r->B), dim3(RG_THREADS), (size_t)r->npmax * sizeof(float), s, r->spec, Y,
                      (const float*)W, (const float*)logV, r->DT, r->colc, r->band, p.warm, r->Yg, r->V, r->U, r->A,
                      r->Wst, r->done, r->status, r->iters, r->ew_prev, r->ew_best, r->stall, r->flags + 1);

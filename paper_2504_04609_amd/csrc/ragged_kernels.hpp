@@ -31,9 +31,14 @@ struct RgSpec {
   long long dt;   // offset of D_b^T ([k, n]) in the transposed copy
   long long col;  // offset of the spectrum's columns in the column tables and the weight state
   long long win;  // offset of w_b in the packed input/output weights
+  long long dp;   // offset of D_b ([n, 64] row-major, zero padded) for the Newton prox; -1: none
 };
 
 constexpr int RG_THREADS = 256;
+// The weight step runs 1024 threads per spectrum: once most spectra have
+// stopped, the last ones are latency bound, and more waves keep more of the
+// dictionary loads in flight.
+constexpr int RG_WS_THREADS = 1024;
 constexpr int RG_MAX_K = 256;
 constexpr int RG_MAX_N = 4096;
 constexpr int RG_TILE_ROWS = 32;
@@ -51,15 +56,15 @@ __device__ __forceinline__ void rg_dict_apply(const float* __restrict__ DTb, con
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     float acc = 0.f;
     int j = 0;
-    for (; j + 4 <= k; j += 4) {
-      float d[4];
+    for (; j + 8 <= k; j += 8) {  // eight independent loads in flight
+      float d[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const int2 bj = bnd[j + q];
         d[q] = (i >= bj.x && i < bj.y) ? DTb[(size_t)(j + q) * n + i] : 0.f;
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc = fmaf(d[q], w[j + q], acc);
+      for (int q = 0; q < 8; ++q) acc = fmaf(d[q], w[j + q], acc);
     }
     for (; j < k; ++j) {
       const int2 bj = bnd[j];
@@ -77,9 +82,9 @@ __device__ __forceinline__ void rg_dict_apply(const float* __restrict__ DTb, con
 // One workgroup per spectrum.
 __global__ __launch_bounds__(RG_THREADS) void rg_prep_dict(const RgSpec* __restrict__ spec, const float* __restrict__ D,
                                                           int pen, double eps, double alpha, double beta,
-                                                          float* __restrict__ DT, float4* __restrict__ colc,
-                                                          int2* __restrict__ band, int* __restrict__ nband,
-                                                          int* __restrict__ bad) {
+                                                          float* __restrict__ DT, float* __restrict__ Dp,
+                                                          float4* __restrict__ colc, int2* __restrict__ band,
+                                                          int* __restrict__ nband, int* __restrict__ bad) {
   __shared__ int nb_s;
   if (threadIdx.x == 0) nb_s = 0;
   const RgSpec sp = spec[blockIdx.x];
@@ -101,6 +106,12 @@ __global__ __launch_bounds__(RG_THREADS) void rg_prep_dict(const RgSpec* __restr
     for (int e = threadIdx.x; e < rows * k; e += blockDim.x) {
       const int c = e / rows, r = e - c * rows;
       DTb[(size_t)c * n + i0 + r] = tile[r * ks + c];
+    }
+    if (sp.dp >= 0) {  // row-major copy with 64 columns for the Newton prox
+      for (int e = threadIdx.x; e < rows * 64; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        Dp[sp.dp + (size_t)(i0 + r) * 64 + c] = c < k ? tile[r * ks + c] : 0.f;
+      }
     }
     if (j < k) {
       for (int r = 0; r < rows; ++r) {
@@ -203,8 +214,10 @@ __global__ __launch_bounds__(RG_THREADS) void rg_init(const RgSpec* __restrict__
 //   u = a / s.
 // Every repetition is one majorize-minimize step on the same ProxP problem, so
 // the fixed point is that of the single step; more steps move w further per
-// kernel product.  Frozen spectra keep their state.
-__global__ __launch_bounds__(RG_THREADS) void rg_weight_step(const RgSpec* __restrict__ spec,
+// kernel product.  Frozen spectra keep their state.  A spectrum whose weights
+// the Newton prox updates (dp >= 0 and *it_dev > newton_after) takes no MM
+// step here: only a = D w and u = a / s at its new weights.
+__global__ __launch_bounds__(RG_WS_THREADS) void rg_weight_step(const RgSpec* __restrict__ spec,
                                                             const float* __restrict__ DT,
                                                             const float4* __restrict__ colc,
                                                             const int2* __restrict__ band, int pen, int inner,
@@ -212,10 +225,12 @@ __global__ __launch_bounds__(RG_THREADS) void rg_weight_step(const RgSpec* __res
                                                             float* __restrict__ U, float* __restrict__ Wst,
                                                             const int* __restrict__ done,
                                                             const int* __restrict__ nband,
-                                                            unsigned long long* __restrict__ work) {
+                                                            unsigned long long* __restrict__ work,
+                                                            const int* __restrict__ it_dev, int newton_after) {
   const int q = blockIdx.x;
   if (done[q]) return;
   const RgSpec sp = spec[q];
+  if (sp.dp >= 0 && newton_after >= 0 && it_dev[0] > newton_after) inner = 0;
   if (work && threadIdx.x == 0)  // algorithmic bytes: s, a in; a, u out; the band of D once; w in and out
     atomicAdd(work, 4ull * (4ull * sp.n + (unsigned long long)nband[q] + 2ull * sp.k));
   const int n = sp.n, k = sp.k, np = sp.np;
@@ -238,6 +253,11 @@ __global__ __launch_bounds__(RG_THREADS) void rg_weight_step(const RgSpec* __res
     bnd[j] = band[sp.col + j];
   }
   __syncthreads();
+  if (inner == 0) {  // weights from the Newton prox: a = D w
+    __syncthreads();
+    rg_dict_apply(DTb, bnd, w, n, k, a_s);
+    __syncthreads();
+  }
   for (int t = 0; t < inner; ++t) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const float a = a_s[i];
@@ -247,14 +267,16 @@ __global__ __launch_bounds__(RG_THREADS) void rg_weight_step(const RgSpec* __res
     for (int j = wave; j < k; j += nwaves) {
       const int2 bj = bnd[j];
       const float* col = DTb + (size_t)j * n;
-      float acc0 = 0.f, acc1 = 0.f;
+      float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
       int i = bj.x + lane;
-      for (; i + 64 < bj.y; i += 128) {
+      for (; i + 192 < bj.y; i += 256) {
         acc0 = fmaf(col[i], r_s[i], acc0);
         acc1 = fmaf(col[i + 64], r_s[i + 64], acc1);
+        acc2 = fmaf(col[i + 128], r_s[i + 128], acc2);
+        acc3 = fmaf(col[i + 192], r_s[i + 192], acc3);
       }
-      if (i < bj.y) acc0 = fmaf(col[i], r_s[i], acc0);
-      const float c = rg_wave_sum(acc0 + acc1);
+      for (; i < bj.y; i += 64) acc0 = fmaf(col[i], r_s[i], acc0);
+      const float c = rg_wave_sum((acc0 + acc1) + (acc2 + acc3));
       if (lane == 0) {
         const float4 cj = cc[j];
         const float wold = w[j];

@@ -33,7 +33,7 @@ EXPORTED = ("otlm_default_params", "otlm_make_kernel", "otlm_free_kernel", "otlm
 PROFILE_CLASSES = ("kv_product", "weight_step", "u_update", "ktu_product", "convergence_test",
                    "kv_product_f64", "weight_prox_f64", "u_update_f64", "ktu_product_f64",
                    "kv_product_bf16", "ktu_product_bf16", "weight_mm_warmup")
-RAGGED_PROFILE_CLASSES = ("kv_product", "weight_step", "ktu_product", "convergence_test")
+RAGGED_PROFILE_CLASSES = ("kv_product", "weight_step", "ktu_product", "convergence_test", "weight_prox_newton")
 RAGGED_TILES = ((128, 128), (128, 64), (64, 128), (64, 64))
 
 
@@ -57,7 +57,8 @@ class AdamW(ctypes.Structure):
 
 
 class RaggedOpts(ctypes.Structure):
-    _fields_ = [("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+    _fields_ = [("use_graph", ctypes.c_int32), ("tile", ctypes.c_int32), ("newton_after", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -276,7 +277,7 @@ class RaggedPlan:
     kdim[b] columns.  Packed layouts as in include/otlm.h."""
 
     def __init__(self, kernels, kernel_of, kdim, params: SolveParams, use_graph: bool = True, tile: int = -1,
-                 stream=None):
+                 newton_after: int = 60, stream=None):
         import numpy as np
         self.kernels = list(kernels)  # the plan reads their K: keep them alive
         self.kernel_of = np.ascontiguousarray(kernel_of, dtype=np.int32)
@@ -296,7 +297,7 @@ class RaggedPlan:
         handles = (ctypes.c_void_p * len(self.kernels))(*[kk.handle for kk in self.kernels])
         o = RaggedOpts()
         lib.otlm_ragged_default_opts(ctypes.byref(o))
-        o.use_graph, o.tile = int(use_graph), int(tile)
+        o.use_graph, o.tile, o.newton_after = int(use_graph), int(tile), int(newton_after)
         p = params.c()
         h = ctypes.c_void_p()
         _check(lib.otlm_ragged_create(handles, len(self.kernels), self.kernel_of.ctypes.data_as(ctypes.c_void_p),

@@ -230,3 +230,26 @@ def test_ragged_workload_full_size_sampled():
     errs = [rel_err(full.w(res, b), full.oracle(b)["W"][0]) for b in pick.values()]
     print("sampled max err", max(errs))
     assert len(errs) == 16 and max(errs) <= 1e-5
+
+
+def test_newton_weight_prox_reaches_oracle(small):
+    """Spectra with k <= 64 switch to the exact weight prox after 3 MM
+    iterations (k = 70 and 130 stay on MM steps): every spectrum still reaches
+    the oracle, in far fewer iterations."""
+    _, mm = small.solve(params(SMALL), newton_after=-1)
+    plan, nt = small.solve(params(SMALL), newton_after=3)
+    assert (nt["status"] == otlm.STATUS_CONVERGED).all()
+    for b in range(SMALL.B):
+        assert rel_err(small.w(nt, b), small.oracle(b)["W"][0]) <= 1e-5, b
+    newton = np.array([k <= 64 for k in small.kdim])
+    print("mean iterations MM", mm["iters"][newton].mean(), "Newton", nt["iters"][newton].mean())
+    assert nt["iters"][newton].mean() < 0.7 * mm["iters"][newton].mean()
+    np.testing.assert_array_equal(nt["iters"][~newton], mm["iters"][~newton])
+
+
+def test_newton_graph_replay_equals_eager(small):
+    p = params(SMALL)
+    _, a = small.solve(p, use_graph=True, tile=0, newton_after=3)
+    _, b = small.solve(p, use_graph=False, tile=0, newton_after=3)
+    for key in ("W", "logV", "iters", "status"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
