@@ -263,10 +263,11 @@ typedef struct {
                           grouped kernel products (128x128, 128x64, 64x128,
                           64x64) on the plan's own shapes at create and keep
                           the fastest; 0..3: use that shape                  */
-  int32_t newton_after;/* 60 (default): a spectrum with kdim <= 64 and n <= 2048
-                          still active after this many iterations takes the
-                          exact weight prox (active-set Newton, as
-                          OTLM_WSTEP_EXACT) instead of MM steps; -1: MM only  */
+  int32_t newton_after;/* 60 (default): a spectrum with kdim <= 128 and
+                          n <= 2048 still active after this many iterations
+                          takes the exact weight prox (active-set Newton, as
+                          OTLM_WSTEP_EXACT; FP64 Hessian for kdim <= 64, FP32
+                          above) instead of MM steps; -1: MM only             */
   int32_t reserved;    /* set to 0                                            */
 } otlm_ragged_opts;
 

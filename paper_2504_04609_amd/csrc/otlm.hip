@@ -514,8 +514,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       ws.validH = nullptr;
       ws.fac_B = 0;
       if (hipMalloc(&ws.Lg, (size_t)B * PN_K * PN_K * sizeof(double)) == hipSuccess &&
-          hipMalloc(&ws.wH, (size_t)B * PN_K * sizeof(double)) == hipSuccess &&
-          hipMalloc(&ws.maskH, (size_t)B * sizeof(unsigned long long)) == hipSuccess &&
+          hipMalloc(&ws.wH, (size_t)B * 128 * sizeof(double)) == hipSuccess &&
+          hipMalloc(&ws.maskH, (size_t)B * 2 * sizeof(unsigned long long)) == hipSuccess &&
           hipMalloc(&ws.validH, (size_t)B * sizeof(int)) == hipSuccess) {
         ws.fac_B = B;
       } else {
@@ -565,7 +565,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<float, float> a;
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = ws.mm_until; a.it = 0;
-    a.nfac = ws.nfac; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
@@ -578,7 +578,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<double, double> a;
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = nullptr; a.it = 0;
-    a.nfac = ws.nfac64; a.Lg = reuse ? ws.Lg : nullptr; a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac64; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;

@@ -65,9 +65,10 @@ struct ProxNewtonArgs {
   int it;
   int* nit;
   int* nfac;                   // Hessian factorisations, accumulated per spectrum
-  double* Lg;                  // [B][64 * 64] last Cholesky factor per spectrum (null: no reuse)
-  double* wH;                  // [B][64] weights at that factorisation
-  unsigned long long* maskH;   // [B] its active set (bit j: w_j pinned at 0)
+  void* Lg;                    // last Cholesky factor per spectrum, lg_stride bytes each (null: no reuse)
+  size_t lg_stride;
+  double* wH;                  // [B][128] weights at that factorisation
+  unsigned long long* maskH;   // [B][2] its active set (bit j: w_j pinned at 0)
   int* validH;                 // [B] 1 when the stored factor may be used
   double reuse_tol;
   const PnSpec* rg;            // ragged layout (null: batch layout)
@@ -163,10 +164,17 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int
   return v + pv;
 }
 
-// MAXB: bins per thread (n <= 256 MAXB); TL: storage of a and of log(a/s) or
-// 1/a in LDS (double for a batch, float for the n <= 2048 of a ragged batch).
-template <class TS, class TW, class TL, int MAXB>
+// Template parameters: MAXB bins per thread (n <= 256 MAXB); TL storage of a
+// and of log(a/s) or 1/a in LDS (double for a batch, float for the n <= 2048
+// of a ragged batch); KMAX the dictionary width the Hessian is laid out for
+// (64, or 128 for ragged spectra with 64 < k <= 128, where the FP64 Hessian
+// and n = 2048 would not fit the 160 KB of LDS); TH the Hessian and Cholesky
+// type (double; float for KMAX = 128: FP32-state ragged solves whose ridge
+// penalty bounds the Hessian's condition number).
+template <class TS, class TW, class TL, int MAXB, int KMAX = PN_K, class TH = double>
 __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<TS, TW> p) {
+  static_assert(KMAX == 64 || KMAX == 128, "dictionary width");
+  constexpr int HLD = KMAX + 1, RPL = KMAX / 64;  // Hessian row stride; rows per lane in the solves
   const int b = blockIdx.x;
   if (p.done[b] || (p.mm_until && p.it <= p.mm_until[b])) return;
   int n = p.n, k = p.k, ld_d = p.ld_d, ld_dt = p.ld_dt, ld_w = p.ld_w;
@@ -177,9 +185,10 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   if (p.rg) {  // ragged: this spectrum's own sizes and arrays, once it is past its MM iterations
     const PnSpec sp = p.rg[b];
     if (sp.dp_off < 0 || p.it_dev[0] <= p.newton_after) return;
+    if ((KMAX == 64) != (sp.k <= 64)) return;  // the other width's kernel takes it
     n = sp.n;
     k = sp.k;
-    ld_d = PN_K;
+    ld_d = KMAX;
     ld_dt = sp.n;
     ld_w = sp.k;
     Dp = p.Dp + sp.dp_off;
@@ -189,49 +198,50 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   }
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* H = smem;                    // [64][65]
-  double* w = H + PN_K * PN_HLD;       // [64]
-  double* wt = w + PN_K;               // [64]
-  double* g = wt + PN_K;               // [64]
-  double* d = g + PN_K;                // [64]
-  double* gp = d + PN_K;               // [4][64] gradient partials
-  double* red = gp + 4 * PN_K;         // [8]
-  TL* a = reinterpret_cast<TL*>(red + 8);  // [n]  D w at the current point
-  TL* l = a + n;                       // [n]  log(a/s) or 1/a
-  TS* s = reinterpret_cast<TS*>(l + n);  // [n]
-  __shared__ int act[PN_K];
+  TH* H = reinterpret_cast<TH*>(smem);                     // [KMAX][KMAX + 1]
+  double* w = reinterpret_cast<double*>(H + KMAX * HLD);   // [KMAX]
+  double* wt = w + KMAX;                                   // [KMAX]
+  double* g = wt + KMAX;                                   // [KMAX]
+  double* d = g + KMAX;                                    // [KMAX]
+  double* gp = d + KMAX;                                   // [4][KMAX] gradient partials
+  double* red = gp + 4 * KMAX;                             // [8]
+  TL* a = reinterpret_cast<TL*>(red + 8);                  // [n]  D w at the current point
+  TL* l = a + n;                                           // [n]  log(a/s) or 1/a
+  TS* s = reinterpret_cast<TS*>(l + n);                    // [n]
+  __shared__ int act[KMAX];
   __shared__ int ctl[4];
-  __shared__ double wHs[PN_K];            // weights of the factor held in H
-  __shared__ unsigned long long hmask_s;  // its active set
+  __shared__ double wHs[KMAX];             // weights of the factor held in H
+  __shared__ unsigned long long hmask_s[RPL];  // its active set
   __shared__ int hstate[2];               // [0] H holds a usable factor, [1] it was rebuilt here
   __shared__ double hrel_diag_s;          // Hessian diagonal entry of a released weight
   __shared__ double kkt_s;                // free-set gradient of this iteration
-  double kkt_prev = 0.0;                  // (thread 0) that of the previous iteration
-  int last_reused = 0;                    // (thread 0) the previous step used a reused factor
   __shared__ int force_rebuild;           // the last reused factor gave no descent
-  if (threadIdx.x == 0) force_rebuild = 0;
+  double kkt_prev = 0.0;                  // (thread 0) the free gradient of the previous iteration
+  int last_reused = 0;                    // (thread 0) the previous step used a reused factor
   int nfac = 0;
 
   for (int i = tid; i < n; i += PN_THREADS) s[i] = srow[i];
-  for (int j = tid; j < PN_K; j += PN_THREADS) {
+  for (int j = tid; j < KMAX; j += PN_THREADS) {
     const double wj = j < k ? (double)wrow[j] : 0.0;
     w[j] = wj > 0.0 ? wj : 0.0;
     act[j] = (j < k && wj > 0.0) ? 0 : 1;   // padded columns stay active at 0
   }
   const bool reuse_on = p.Lg && p.reuse_tol > 0.0;
+  TH* Lb = reuse_on ? reinterpret_cast<TH*>(reinterpret_cast<char*>(p.Lg) + (size_t)b * p.lg_stride) : nullptr;
   if (tid == 0) {
     hstate[0] = reuse_on && p.validH[b];
     hstate[1] = 0;
-    hmask_s = reuse_on ? p.maskH[b] : 0ull;
+    force_rebuild = 0;
+    for (int m = 0; m < RPL; ++m) hmask_s[m] = reuse_on ? p.maskH[(size_t)b * 2 + m] : 0ull;
   }
   __syncthreads();
   if (hstate[0]) {  // the factor of the previous launch
-    const double* Lb = p.Lg + (size_t)b * PN_K * PN_K;
-    for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) H[(e >> 6) * PN_HLD + (e & 63)] = Lb[e];
-    if (tid < PN_K) wHs[tid] = p.wH[(size_t)b * PN_K + tid];
+    for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) H[(e / KMAX) * HLD + (e % KMAX)] = Lb[e];
+    if (tid < KMAX) wHs[tid] = p.wH[(size_t)b * 128 + tid];
   }
   __syncthreads();
   const double tiny = sizeof(TL) == 4 ? 1e-30 : 1e-300;
+  const TH tinyh = sizeof(TH) == 4 ? (TH)1e-30 : (TH)1e-300;
   const double gscale = fmax(fmax(p.alpha, p.eps), 1e-300) * p.gtol;
   const double hpen = p.pen == PEN_L2SQ ? p.alpha : (p.pen == PEN_EN ? p.beta : 0.0);
 
@@ -242,25 +252,29 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)log(fmax((double)a[i], tiny) / (double)s[i]);
     __syncthreads();
     {
-      // thread (j = lane, q = wave) sums bins i = q, q + 4, ... of column j;
+      // thread (j = lane + 64 cc, q = wave) sums bins i = q, q + 4, ... of column j;
       // eight independent partial sums keep the D loads in flight
-      const int j = lane, q = wave;
-      double part[8];
+      const int q = wave;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) part[u] = 0.0;
-      if (j < k) {
-        const float* dcol = Dp + j;
-        int i = q;
-        for (; i + 28 < n; i += 32) {
+      for (int cc = 0; cc < RPL; ++cc) {
+        const int j = lane + 64 * cc;
+        double part[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * ld_d] * (double)l[i + 4 * u];
+        for (int u = 0; u < 8; ++u) part[u] = 0.0;
+        if (j < k) {
+          const float* dcol = Dp + j;
+          int i = q;
+          for (; i + 28 < n; i += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * ld_d] * (double)l[i + 4 * u];
+          }
+          for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * ld_d] * (double)l[i];
         }
-        for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * ld_d] * (double)l[i];
+        gp[q * KMAX + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
       }
-      gp[q * PN_K + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
       __syncthreads();
-      if (tid < PN_K) {
-        const double gj = (gp[tid] + gp[PN_K + tid]) + (gp[2 * PN_K + tid] + gp[3 * PN_K + tid]);
+      if (tid < KMAX) {
+        const double gj = (gp[tid] + gp[KMAX + tid]) + (gp[2 * KMAX + tid] + gp[3 * KMAX + tid]);
         g[tid] = tid < k ? pn_pen_grad(p.pen, w[tid], p.alpha, p.beta) + p.eps * gj : 0.0;
       }
       __syncthreads();
@@ -292,14 +306,17 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     if (ctl[0]) break;
     const int released = ctl[1];
     if (tid == 0) {  // reuse the factor held in H?
-      unsigned long long mask = 0ull;
+      unsigned long long mask[RPL];
+      for (int m = 0; m < RPL; ++m) mask[m] = 0ull;
       for (int j = 0; j < k; ++j)
-        if (act[j]) mask |= 1ull << j;
+        if (act[j]) mask[j >> 6] |= 1ull << (j & 63);
+      bool same = true;
+      for (int m = 0; m < RPL; ++m) same = same && mask[m] == hmask_s[m];
       int reuse = 0;
       // a step on a reused factor that did not halve the free gradient: refactor
       const bool poor = (last_reused && kkt_s > 0.5 * kkt_prev) || force_rebuild;
       force_rebuild = 0;
-      if (hstate[0] && released < 0 && mask == hmask_s && !poor) {
+      if (hstate[0] && released < 0 && same && !poor) {
         double dm = 0.0, wm = 0.0;
         for (int j = 0; j < k; ++j) {
           dm = fmax(dm, fabs(w[j] - wHs[j]));
@@ -308,115 +325,142 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
         reuse = dm <= p.reuse_tol * wm;
       }
       ctl[3] = reuse;
-      if (!reuse) hmask_s = mask;
+      if (!reuse)
+        for (int m = 0; m < RPL; ++m) hmask_s[m] = mask[m];
       last_reused = reuse;
       kkt_prev = kkt_s;
     }
     __syncthreads();
     if (!ctl[3]) {
-
-    // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
-    for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)(1.0 / fmax((double)a[i], tiny));
-    __syncthreads();
-    {
-      // 128 register blocks of 8 x 4 entries (block row bj = 0..7, block column
-      // bl = 0..15) over two bin groups (bins of parity q)
-      const int q = tid >> 7, blk = tid & 127, bj = blk >> 4, bl = blk & 15;
-      double acc[8][4];
-#pragma unroll
-      for (int x = 0; x < 8; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      const float* rowj = Dp + bj * 8;
-      const float* rowl = Dp + bl * 4;
-      for (int i = q; i < n; i += 2) {
-        const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
-        const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
-        const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
-        const double sc = l[i];  // 1 / a_i
-        const double xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
-        const double xb[4] = {(double)lv.x, (double)lv.y, (double)lv.z, (double)lv.w};
+      // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
+      for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)(1.0 / fmax((double)a[i], tiny));
+      __syncthreads();
+      if constexpr (KMAX == 64) {
+        // 128 register blocks of 8 x 4 entries (block row bj = 0..7, block column
+        // bl = 0..15) over two bin groups (bins of parity q)
+        const int q = tid >> 7, blk = tid & 127, bj = blk >> 4, bl = blk & 15;
+        double acc[8][4];
 #pragma unroll
         for (int x = 0; x < 8; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += xa[x] * xb[y];
-      }
-      // fold the two bin groups into H
-      for (int grp = 0; grp < 2; ++grp) {
-        if (q == grp) {
+          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        const float* rowj = Dp + bj * 8;
+        const float* rowl = Dp + bl * 4;
+        for (int i = q; i < n; i += 2) {
+          const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
+          const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
+          const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
+          const double sc = l[i];  // 1 / a_i
+          const double xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
+          const double xb[4] = {(double)lv.x, (double)lv.y, (double)lv.z, (double)lv.w};
 #pragma unroll
           for (int x = 0; x < 8; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) {
-              double* h = &H[(bj * 8 + x) * PN_HLD + bl * 4 + y];
-              *h = (grp == 0 ? 0.0 : *h) + acc[x][y];
+            for (int y = 0; y < 4; ++y) acc[x][y] += xa[x] * xb[y];
+        }
+        // fold the two bin groups into H
+        for (int grp = 0; grp < 2; ++grp) {
+          if (q == grp) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y) {
+                TH* h = &H[(bj * 8 + x) * HLD + bl * 4 + y];
+                *h = (grp == 0 ? (TH)0 : *h) + (TH)acc[x][y];
+              }
+          }
+          __syncthreads();
+        }
+      } else {
+        // 256 register blocks of 8 x 8 entries (block row bj, block column bl = 0..15)
+        const int bj = tid >> 4, bl = tid & 15;
+        TH acc[8][8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+          for (int y = 0; y < 8; ++y) acc[x][y] = (TH)0;
+        const float* rowj = Dp + bj * 8;
+        const float* rowl = Dp + bl * 8;
+        for (int i = 0; i < n; ++i) {
+          const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
+          const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
+          const float4 la = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
+          const float4 lb = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d + 4);
+          const TH sc = (TH)l[i];  // 1 / a_i
+          const TH xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
+          const TH xb[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+#pragma unroll
+          for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int y = 0; y < 8; ++y) acc[x][y] += xa[x] * xb[y];
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+          for (int y = 0; y < 8; ++y) H[(bj * 8 + x) * HLD + bl * 8 + y] = acc[x][y];
+        __syncthreads();
+      }
+      // scale, add the penalty curvature, and pin the active weights (identity rows)
+      for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) {
+        const int r = e / KMAX, c = e % KMAX;
+        double h = p.eps * (double)H[r * HLD + c];
+        if (act[r] || act[c]) h = (r == c) ? 1.0 : 0.0;
+        else if (r == c) h += hpen;
+        H[r * HLD + c] = (TH)h;
+      }
+      __syncthreads();
+      if (tid == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
+      __syncthreads();
+
+      // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
+      // the diagonal tile in one wave, solve the panel below it (one thread per
+      // row), update the trailing lower triangle (all threads).
+      for (int kk = 0; kk < KMAX; kk += 16) {
+        if (wave == 0 && lane < 16) {
+          const int r = kk + lane;
+          TH* Hr = H + r * HLD;
+          for (int c = kk; c < kk + 16; ++c) {
+            TH acc = 0;
+            if (r >= c) {
+              const TH* Hc = H + c * HLD;
+              acc = Hr[c];
+              for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
             }
+            if (r == c) Hr[c] = sqrt(acc > (TH)0 ? acc : tinyh);
+            pn_wave_sync();
+            if (r > c) Hr[c] = acc / H[c * HLD + c];
+            pn_wave_sync();
+          }
+        }
+        __syncthreads();
+        for (int r = kk + 16 + tid; r < KMAX; r += PN_THREADS) {
+          TH* Hr = H + r * HLD;
+          for (int c = kk; c < kk + 16; ++c) {
+            const TH* Hc = H + c * HLD;
+            TH acc = Hr[c];
+            for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
+            Hr[c] = acc / Hc[c];
+          }
+        }
+        __syncthreads();
+        const int m = KMAX - kk - 16;
+        for (int e = tid; e < m * m; e += PN_THREADS) {
+          const int r = kk + 16 + e / m, c = kk + 16 + e % m;
+          if (c <= r) {
+            const TH* Hr = H + r * HLD;
+            const TH* Hc = H + c * HLD;
+            TH s0 = 0, s1 = 0;
+#pragma unroll
+            for (int q = 0; q < 16; q += 2) {
+              s0 += Hr[kk + q] * Hc[kk + q];
+              s1 += Hr[kk + q + 1] * Hc[kk + q + 1];
+            }
+            H[r * HLD + c] -= s0 + s1;
+          }
         }
         __syncthreads();
       }
-    }
-    // scale, add the penalty curvature, and pin the active weights (identity rows)
-    for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) {
-      const int r = e >> 6, c = e & 63;
-      double h = p.eps * H[r * PN_HLD + c];
-      if (act[r] || act[c]) h = (r == c) ? 1.0 : 0.0;
-      else if (r == c) h += hpen;
-      H[r * PN_HLD + c] = h;
-    }
-    __syncthreads();
-    if (tid == 0) hrel_diag_s = released >= 0 ? H[released * PN_HLD + released] : 1.0;
-    __syncthreads();
-
-    // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
-    // the diagonal tile in one wave, solve the panel below it (one thread per
-    // row), update the trailing lower triangle (all threads), four rounds.
-    for (int kk = 0; kk < PN_K; kk += 16) {
-      if (wave == 0 && lane < 16) {
-        const int r = kk + lane;
-        double* Hr = H + r * PN_HLD;
-        for (int c = kk; c < kk + 16; ++c) {
-          double acc = 0.0;
-          if (r >= c) {
-            const double* Hc = H + c * PN_HLD;
-            acc = Hr[c];
-            for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
-          }
-          if (r == c) Hr[c] = sqrt(acc > 0.0 ? acc : 1e-300);
-          pn_wave_sync();
-          if (r > c) Hr[c] = acc / H[c * PN_HLD + c];
-          pn_wave_sync();
-        }
-      }
-      __syncthreads();
-      for (int r = kk + 16 + tid; r < PN_K; r += PN_THREADS) {
-        double* Hr = H + r * PN_HLD;
-        for (int c = kk; c < kk + 16; ++c) {
-          const double* Hc = H + c * PN_HLD;
-          double acc = Hr[c];
-          for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
-          Hr[c] = acc / Hc[c];
-        }
-      }
-      __syncthreads();
-      const int m = PN_K - kk - 16;
-      for (int e = tid; e < m * m; e += PN_THREADS) {
-        const int r = kk + 16 + e / m, c = kk + 16 + e % m;
-        if (c <= r) {
-          const double* Hr = H + r * PN_HLD;
-          const double* Hc = H + c * PN_HLD;
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int q = 0; q < 16; q += 2) {
-            s0 += Hr[kk + q] * Hc[kk + q];
-            s1 += Hr[kk + q + 1] * Hc[kk + q + 1];
-          }
-          H[r * PN_HLD + c] -= s0 + s1;
-        }
-      }
-      __syncthreads();
-    }
-
-      if (tid < PN_K) wHs[tid] = w[tid];
+      if (tid < KMAX) wHs[tid] = w[tid];
       if (tid == 0) {
         hstate[0] = 1;
         hstate[1] = 1;
@@ -424,39 +468,61 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       ++nfac;
       __syncthreads();
     }
-    const double hrel_diag_used = released >= 0 ? hrel_diag_s : 1.0;
+    const double hdiag_released = released >= 0 ? hrel_diag_s : 1.0;
 
-    // ---- solve L L^T d = -g in wave 0 (lane r owns row r)
+    // ---- solve L L^T d = -g in wave 0 (lane owns rows lane + 64 rr)
     if (wave == 0) {
-      const int r = lane;
-      const double hdiag_released = hrel_diag_used;
-      const double* Hr = H + r * PN_HLD;
       // forward: L y = -g ; backward: L^T d = y   (active rows: g = 0, L row = e_r)
-      double y = act[r] ? 0.0 : -g[r];
-      for (int c = 0; c < PN_K; ++c) {
-        const double yc = __shfl(y, c, 64) / H[c * PN_HLD + c];
-        if (r == c) y = yc;
-        else if (r > c) y -= Hr[c] * yc;
+      double y[RPL];
+#pragma unroll
+      for (int rr = 0; rr < RPL; ++rr) {
+        const int r = lane + 64 * rr;
+        y[rr] = act[r] ? 0.0 : -g[r];
       }
-      for (int c = PN_K - 1; c >= 0; --c) {
-        const double dc = __shfl(y, c, 64) / H[c * PN_HLD + c];
-        if (r == c) y = dc;
-        else if (r < c) y -= H[c * PN_HLD + r] * dc;
+      for (int c = 0; c < KMAX; ++c) {
+        const double yc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int r = lane + 64 * rr;
+          if (r == c) y[rr] = yc;
+          else if (r > c) y[rr] -= (double)H[r * HLD + c] * yc;
+        }
+      }
+      for (int c = KMAX - 1; c >= 0; --c) {
+        const double dc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int r = lane + 64 * rr;
+          if (r == c) y[rr] = dc;
+          else if (r < c) y[rr] -= (double)H[c * HLD + r] * dc;
+        }
       }
       // weights at 0 cannot decrease; a released weight swamped by the coupling
       // takes its own Newton coordinate step instead
-      if (w[r] <= 0.0 && y < 0.0) y = 0.0;
-      const double yr = __shfl(y, released >= 0 ? released : 0, 64);
-      if (released >= 0 && yr <= 0.0) y = (r == released) ? -g[r] / hdiag_released : 0.0;
-      d[r] = act[r] ? 0.0 : y;
+      const int rel = released >= 0 ? released : 0;
+      double yr = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < RPL; ++rr) {
+        const int r = lane + 64 * rr;
+        if (w[r] <= 0.0 && y[rr] < 0.0) y[rr] = 0.0;
+        const double v = __shfl(y[rr], rel & 63, 64);
+        if ((rel >> 6) == rr) yr = v;
+      }
+#pragma unroll
+      for (int rr = 0; rr < RPL; ++rr) {
+        const int r = lane + 64 * rr;
+        double yv = y[rr];
+        if (released >= 0 && yr <= 0.0) yv = (r == released) ? -g[r] / hdiag_released : 0.0;
+        d[r] = act[r] ? 0.0 : yv;
+      }
     }
     __syncthreads();
 
     // ---- ratio test and Armijo backtracking
     double slope = 0.0, tmax = INFINITY;
     {
-      const double sl = (tid < PN_K && !act[tid]) ? g[tid] * d[tid] : 0.0;
-      const double tm = (tid < PN_K && !act[tid] && d[tid] < 0.0) ? -w[tid] / d[tid] : INFINITY;
+      const double sl = (tid < KMAX && !act[tid]) ? g[tid] * d[tid] : 0.0;
+      const double tm = (tid < KMAX && !act[tid] && d[tid] < 0.0) ? -w[tid] / d[tid] : INFINITY;
       slope = pn_block_sum(sl, red);
       tmax = pn_block_min(tm, red);
     }
@@ -465,12 +531,12 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     if (slope < 0.0 && -slope <= 1e-14 * fabs(f)) {
       // the predicted decrease is below what V can resolve in FP64: the point is
       // optimal to working precision on this free set, take the step untested
-      if (tid < PN_K) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
+      if (tid < KMAX) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
       __syncthreads();
       accepted = true;
     } else if (slope < 0.0) {
       for (int ls = 0; ls < 30; ++ls) {
-        if (tid < PN_K) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
+        if (tid < KMAX) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
         __syncthreads();
         const double fn = pn_eval<MAXB>(p, DTp, ld_dt, n, k, wt, s, (TL*)nullptr, red);
         if (fn <= f + 1e-4 * t * slope) {
@@ -497,7 +563,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       break;
     }
     const bool hit = (t == tmax);
-    if (tid < PN_K) {
+    if (tid < KMAX) {
       double wn = wt[tid];
       // the weights that stop the ratio test join the active set at exactly 0
       if (hit && !act[tid] && d[tid] < 0.0 && -w[tid] / d[tid] <= tmax * (1.0 + 1e-12)) {
@@ -511,22 +577,25 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
 
   // ---- write back (and the last factor, for the next launch)
   if (tid < k) wrow[tid] = (TW)w[tid];
-  if (tid < PN_K && tid >= k && tid < ld_w) wrow[tid] = (TW)0;
+  if (tid < KMAX && tid >= k && tid < ld_w) wrow[tid] = (TW)0;
   if (tid == 0) {
     p.nit[b] += it;
     if (p.nfac) p.nfac[b] += nfac;
   }
   if (reuse_on && hstate[1]) {
-    double* Lb = p.Lg + (size_t)b * PN_K * PN_K;
-    for (int e = tid; e < PN_K * PN_K; e += PN_THREADS) Lb[e] = H[(e >> 6) * PN_HLD + (e & 63)];
-    if (tid < PN_K) p.wH[(size_t)b * PN_K + tid] = wHs[tid];
+    for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) Lb[e] = H[(e / KMAX) * HLD + (e % KMAX)];
+    if (tid < KMAX) p.wH[(size_t)b * 128 + tid] = wHs[tid];
     if (tid == 0) {
-      p.maskH[b] = hmask_s;
+      for (int m = 0; m < RPL; ++m) p.maskH[(size_t)b * 2 + m] = hmask_s[m];
       p.validH[b] = 1;
     }
   }
 }
 
+// Dynamic LDS of prox_newton_kernel<..., KMAX, TH> for n bins, s elements of
+// s_bytes and a / l elements of l_bytes.
+template <int KMAX = PN_K, class TH = double>
 inline size_t prox_newton_smem(int n, size_t s_bytes, size_t l_bytes = sizeof(double)) {
-  return sizeof(double) * ((size_t)PN_K * PN_HLD + 8 * PN_K + 8) + (2 * l_bytes + s_bytes) * (size_t)n;
+  return sizeof(TH) * (size_t)KMAX * (KMAX + 1) + sizeof(double) * (8 * (size_t)KMAX + 8) +
+         (2 * l_bytes + s_bytes) * (size_t)n;
 }

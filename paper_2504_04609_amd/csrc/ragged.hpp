@@ -20,6 +20,7 @@ enum { RG_PROF_KV = 0, RG_PROF_W, RG_PROF_KTU, RG_PROF_CHECK, RG_PROF_NEWTON, RG
 // gradient tolerance (FP32 state, a and log(a/s) held in FP32).
 constexpr int RG_NEWTON_MAX = 5;
 constexpr double RG_NEWTON_GTOL = 1e-7;
+constexpr size_t RG_LG_STRIDE = 65536;  // bytes of stored factor per spectrum: 64^2 FP64 or 128^2 FP32
 
 }  // namespace
 
@@ -45,7 +46,8 @@ struct otlm_ragged_s {
   int* nband = nullptr;       // band entries of each spectrum's dictionary
   // Newton prox of the spectra still active after newton_after iterations (k <= 64, n <= 2048)
   int newton_after = -1;
-  int n_newton = 0, nmax_newton = 0;  // spectra that may take it, their largest n
+  int n_newton = 0, nmax64 = 0, nmax128 = 0;  // spectra that may take it; largest n with k <= 64 / k > 64
+  size_t smem64 = 0, smem128 = 0;
   int64_t tot_dp = 0;
   float* Dp = nullptr;
   PnSpec* pnspec = nullptr;
@@ -219,13 +221,19 @@ void rg_iterate(otlm_ragged_s* r, bool chk, hipStream_t s) {
     ProxNewtonArgs<float, float> a{};
     a.S = r->S; a.W = r->Wst; a.Dp = r->Dp; a.DTp = r->DT; a.colc = r->colc; a.done = r->done;
     a.mm_until = nullptr; a.it = 0; a.nit = r->nit; a.nfac = r->nfac;
-    a.Lg = r->Lg; a.wH = r->wH; a.maskH = r->maskH; a.validH = r->validH; a.reuse_tol = OTLM_HESS_REUSE;
+    a.Lg = r->Lg; a.lg_stride = RG_LG_STRIDE; a.wH = r->wH; a.maskH = r->maskH; a.validH = r->validH;
+    a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = r->pnspec; a.it_dev = r->it_dev; a.newton_after = r->newton_after;
     a.pen = r->p.pen; a.max_newton = RG_NEWTON_MAX; a.eps = r->p.eps; a.alpha = r->p.alpha; a.beta = r->p.beta;
     a.gtol = RG_NEWTON_GTOL;
-    auto kern = prox_newton_kernel<float, float, float, PN_MAXB_RAGGED>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)r->B), dim3(PN_THREADS),
-                       prox_newton_smem(r->nmax_newton, sizeof(float), sizeof(float)), s, a);
+    if (r->nmax64) {
+      auto kern = prox_newton_kernel<float, float, float, PN_MAXB_RAGGED, 64, double>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)r->B), dim3(PN_THREADS), r->smem64, s, a);
+    }
+    if (r->nmax128) {
+      auto kern = prox_newton_kernel<float, float, float, PN_MAXB_RAGGED, 128, float>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)r->B), dim3(PN_THREADS), r->smem128, s, a);
+    }
   }
   {
     RgProfScope ps(r, RG_PROF_W, s);
@@ -433,14 +441,25 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
     odt += (int64_t)G.n * kdim[b];
     ocol += kdim[b];
     sp.dp = -1;
-    if (r->newton_after >= 0 && sp.k <= PN_K && sp.n <= PN_THREADS * PN_MAXB_RAGGED) {
+    if (r->newton_after >= 0 && sp.k <= 128 && sp.n <= PN_THREADS * PN_MAXB_RAGGED) {
       sp.dp = odp;
-      odp += (int64_t)sp.n * PN_K;
+      odp += (int64_t)sp.n * (sp.k <= 64 ? 64 : 128);
       r->n_newton += 1;
-      r->nmax_newton = std::max(r->nmax_newton, sp.n);
+      if (sp.k <= 64) r->nmax64 = std::max(r->nmax64, sp.n);
+      else r->nmax128 = std::max(r->nmax128, sp.n);
     }
   }
   r->tot_dp = odp;
+  r->smem64 = r->nmax64 ? prox_newton_smem<64, double>(r->nmax64, sizeof(float), sizeof(float)) : 0;
+  r->smem128 = r->nmax128 ? prox_newton_smem<128, float>(r->nmax128, sizeof(float), sizeof(float)) : 0;
+  if (r->smem64 > 65536 &&
+      hipFuncSetAttribute((const void*)prox_newton_kernel<float, float, float, PN_MAXB_RAGGED, 64, double>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)r->smem64) != hipSuccess)
+    return fail(OTLM_E_HIP);
+  if (r->smem128 > 65536 &&
+      hipFuncSetAttribute((const void*)prox_newton_kernel<float, float, float, PN_MAXB_RAGGED, 128, float>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)r->smem128) != hipSuccess)
+    return fail(OTLM_E_HIP);
   std::vector<PnSpec> hpn(B);
   for (int64_t q = 0; q < B; ++q) {
     const RgSpec& sp = r->hspec[q];
@@ -456,8 +475,9 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
             r->alloc(&r->stall, B) && r->alloc(&r->it_dev, 1) && r->alloc(&r->act, 1) &&
             r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 2) &&
             r->alloc(&r->Dp, r->tot_dp) && r->alloc(&r->pnspec, B) && r->alloc(&r->nit, B) &&
-            r->alloc(&r->nfac, B) && r->alloc(&r->validH, B) && r->alloc(&r->maskH, B) &&
-            r->alloc(&r->wH, r->n_newton ? B * PN_K : 1) && r->alloc(&r->Lg, r->n_newton ? B * PN_K * PN_K : 1);
+            r->alloc(&r->nfac, B) && r->alloc(&r->validH, B) && r->alloc(&r->maskH, 2 * B) &&
+            r->alloc(&r->wH, r->n_newton ? B * 128 : 1) &&
+            r->alloc(&r->Lg, r->n_newton ? (size_t)B * (RG_LG_STRIDE / sizeof(double)) : 1);
   if (!ok) return fail(OTLM_E_NOMEM);
   if (hipHostMalloc((void**)&r->host_flags, 4 * sizeof(int)) != hipSuccess) return fail(OTLM_E_NOMEM);
   const size_t sb = (size_t)r->tot_state * sizeof(float);

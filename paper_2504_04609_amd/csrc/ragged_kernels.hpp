@@ -31,7 +31,8 @@ struct RgSpec {
   long long dt;   // offset of D_b^T ([k, n]) in the transposed copy
   long long col;  // offset of the spectrum's columns in the column tables and the weight state
   long long win;  // offset of w_b in the packed input/output weights
-  long long dp;   // offset of D_b ([n, 64] row-major, zero padded) for the Newton prox; -1: none
+  long long dp;   // offset of D_b ([n, 64] row-major if k <= 64, else [n, 128]; zero padded) for the
+                  // Newton prox; -1: none
 };
 
 constexpr int RG_THREADS = 256;
@@ -107,10 +108,11 @@ __global__ __launch_bounds__(RG_THREADS) void rg_prep_dict(const RgSpec* __restr
       const int c = e / rows, r = e - c * rows;
       DTb[(size_t)c * n + i0 + r] = tile[r * ks + c];
     }
-    if (sp.dp >= 0) {  // row-major copy with 64 columns for the Newton prox
-      for (int e = threadIdx.x; e < rows * 64; e += blockDim.x) {
-        const int r = e >> 6, c = e & 63;
-        Dp[sp.dp + (size_t)(i0 + r) * 64 + c] = c < k ? tile[r * ks + c] : 0.f;
+    if (sp.dp >= 0) {  // row-major copy with 64 or 128 columns for the Newton prox
+      const int wdt = k <= 64 ? 64 : 128;
+      for (int e = threadIdx.x; e < rows * wdt; e += blockDim.x) {
+        const int r = e / wdt, c = e - r * wdt;
+        Dp[sp.dp + (size_t)(i0 + r) * wdt + c] = c < k ? tile[r * ks + c] : 0.f;
       }
     }
     if (j < k) {
