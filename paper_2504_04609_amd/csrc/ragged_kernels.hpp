@@ -36,10 +36,11 @@ struct RgSpec {
 };
 
 constexpr int RG_THREADS = 256;
-// The weight step runs 1024 threads per spectrum: once most spectra have
-// stopped, the last ones are latency bound, and more waves keep more of the
-// dictionary loads in flight.
-constexpr int RG_WS_THREADS = 1024;
+// Threads of the weight step per spectrum (256: many spectra in flight in the
+// bulk of a solve; the slow tail takes the Newton prox instead).
+#ifndef RG_WS_THREADS
+#define RG_WS_THREADS 256
+#endif
 constexpr int RG_MAX_K = 256;
 constexpr int RG_MAX_N = 4096;
 constexpr int RG_TILE_ROWS = 32;
