@@ -108,13 +108,16 @@ def roofline(prof, B, n, k, phi):
         peak = {"f64": PEAK["fp64_mfma"], "bf16": PEAK["bf16_mfma"]}.get(dom.rsplit("_", 1)[-1], PEAK["fp32_mfma"])
         entry.update(bound="mfma", unit="TFLOP/s", peak=peak, flops_per_launch=flops)
     elif dom in ("weight_step", "weight_prox_f64") and prof["newton_iters"] > 0:
-        # Newton on the weight prox (FP64 arithmetic): per Newton iteration and
-        # spectrum the Hessian build is 2 n 64^2 flop (dense 64 x 64), gradient and
-        # line-search evaluations ~6 n k; the Newton iterations of this kernel
-        # (FP32- or FP64-state) over its timed launches.
-        nit = prof["newton_iters_fp32"] if dom == "weight_step" else prof["newton_iters_fp64"]
-        per_newton = 2.0 * n * 64 * 64 + 6.0 * n * k
-        flops = nit * per_newton / max(cnt, 1)
+        # Newton on the weight prox (FP64 arithmetic): every Newton iteration and
+        # spectrum takes ~6 n k flop (a = D w and the objective, the gradient, one
+        # line-search evaluation); an iteration that factors anew adds the Hessian's
+        # lower-triangle blocks, 2 n (10/16) 64^2, and the Cholesky factorisation,
+        # 64^3 / 3; the counts are those of this kernel (FP32- or FP64-state) over
+        # its timed launches.
+        sfx = "fp32" if dom == "weight_step" else "fp64"
+        nit, nfac = prof["newton_iters_" + sfx], prof["factorisations_" + sfx]
+        flops = (nit * 6.0 * n * k + nfac * (2.0 * n * 64 * 64 * 10 / 16 + 64.0 ** 3 / 3)) / max(cnt, 1)
+        entry.update(newton_iters=nit, factorisations=nfac)
         entry["kernel"] = "prox_newton_kernel<float, float>" if dom == "weight_step" else \
             "prox_newton_kernel<double, double>"
         entry.update(bound="alu", unit="TFLOP/s", peak=PEAK["fp64_vector"], flops_per_launch=flops)

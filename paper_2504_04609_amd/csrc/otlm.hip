@@ -474,7 +474,15 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   if (B > (1 << 24)) return OTLM_E_INVALID;
   const bool exact = p->wstep == OTLM_WSTEP_EXACT;
   const bool fp64 = p->refine == OTLM_REFINE_FP64;
-  if (exact && (kdim > PN_K || prox_newton_smem((int)k->n, sizeof(double)) > 65536)) return OTLM_E_UNSUPPORTED;
+  if (exact && (kdim > PN_K || prox_newton_smem((int)k->n, sizeof(double)) > PN_LDS_MAX)) return OTLM_E_UNSUPPORTED;
+  if (exact) {  // the Newton kernels take more than the default 64 KB of dynamic LDS
+    const size_t sm32 = prox_newton_smem((int)k->n, sizeof(float)), sm64 = prox_newton_smem((int)k->n, sizeof(double));
+    if (hipFuncSetAttribute((const void*)prox_newton_kernel<float, float, double, PN_MAXB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm32) != hipSuccess ||
+        (fp64 && hipFuncSetAttribute((const void*)prox_newton_kernel<double, double, double, PN_MAXB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm64) != hipSuccess))
+      return OTLM_E_HIP;
+  }
   if (fp64 && !exact) return OTLM_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = k->n, np = k->np, kp = round_up(kdim, 64);

@@ -17,11 +17,16 @@
 //
 // One workgroup (256 threads, 4 wave64s) per spectrum, everything in FP64 (the
 // Hessian of an overlapping Gaussian dictionary has condition numbers near
-// 1e12).  LDS holds s, a = D w and log(a/s) or 1/sqrt(a) for the n bins and the
-// 64 x 64 Hessian: (16 + sizeof(s)) n + 35 KB, so n <= 1024 fits in 64 KB.
+// 1e12).  LDS holds s and two pairs (a = D w, log(a/s)) for the n bins, the
+// current point's and the line search's, and the 64 x 64 Hessian:
+// (4 sizeof(a) + sizeof(s)) n + 37 KB, 78 KB at n = 1024 (two workgroups per CU).
+// An accepted trial point keeps the a, log(a/s) and objective value the line
+// search computed, so a Newton iteration after a line-search step starts
+// without another pass over the dictionary.
 // The dictionary is streamed from L2 with many independent loads in flight
-// (D^T for the bin sweeps, D for the column sweeps).  The Hessian is built with
-// 8 x 4 register blocks per thread over two bin groups; the Cholesky
+// (D^T for the bin sweeps, D for the column sweeps).  The 64-wide Hessian is
+// built on the FP64 matrix cores (its lower-triangle 16 x 16 blocks, each wave
+// over a quarter of the bins, every dictionary entry read once); the Cholesky
 // factorisation runs by 16 x 16 tiles and the two triangular solves in one wave,
 // one row per lane.
 //
@@ -35,6 +40,7 @@
 // gradient; otherwise it builds and factors the Hessian anew.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "gemm_nt_f64.hpp"
 #include "solver_kernels.hpp"
 
 constexpr int PN_THREADS = 256;
@@ -117,11 +123,12 @@ __device__ __forceinline__ double pn_pen_grad(int pen, double w, double alpha, d
 }
 
 // V(w) = eps sum_i (a_i log(a_i/s_i) - a_i + s_i) + sum_j alpha R(w_j), a = D w
-// (bins with a = 0 give s_i); stores a when `a` is not null.  Each thread owns
-// up to PN_MAXB bins and keeps their sums independent so the D^T loads overlap.
+// (bins with a = 0 give s_i); stores a and l = log(max(a, tiny) / s), the
+// factor of the gradient.  Each thread owns up to MAXB bins and keeps their
+// sums independent so the D^T loads overlap.
 template <int MAXB, class TS, class TW, class TL>
 __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int ld_dt, int n, int k,
-                          const double* w, const TS* s, TL* a, double* red) {
+                          const double* w, const TS* s, TL* a, TL* l, double tiny, double* red) {
   double ai[MAXB];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) ai[q] = 0.0;
@@ -153,9 +160,11 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int
   for (int q = 0; q < MAXB; ++q) {
     const int i = threadIdx.x + q * PN_THREADS;
     if (i < n) {
-      if (a) a[i] = (TL)ai[q];
       const double si = (double)s[i];
-      acc += (ai[q] > 0.0 ? ai[q] * log(ai[q] / si) : 0.0) - ai[q] + si;
+      const double lg = log(fmax(ai[q], tiny) / si);
+      a[i] = (TL)ai[q];
+      l[i] = (TL)lg;
+      acc += (ai[q] > 0.0 ? ai[q] * lg : 0.0) - ai[q] + si;
     }
   }
   double v = p.eps * pn_block_sum(acc, red);
@@ -172,8 +181,9 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int
 // type (double; float for KMAX = 128: FP32-state ragged solves whose ridge
 // penalty bounds the Hessian's condition number).
 template <class TS, class TW, class TL, int MAXB, int KMAX = PN_K, class TH = double>
-__global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<TS, TW> p) {
+__global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonArgs<TS, TW> p) {
   static_assert(KMAX == 64 || KMAX == 128, "dictionary width");
+  static_assert(KMAX == 128 || sizeof(TH) == 8, "the 64-wide Hessian is built in FP64");
   constexpr int HLD = KMAX + 1, RPL = KMAX / 64;  // Hessian row stride; rows per lane in the solves
   const int b = blockIdx.x;
   if (p.done[b] || (p.mm_until && p.it <= p.mm_until[b])) return;
@@ -205,9 +215,14 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   double* d = g + KMAX;                                    // [KMAX]
   double* gp = d + KMAX;                                   // [4][KMAX] gradient partials
   double* red = gp + 4 * KMAX;                             // [8]
-  TL* a = reinterpret_cast<TL*>(red + 8);                  // [n]  D w at the current point
-  TL* l = a + n;                                           // [n]  log(a/s) or 1/a
-  TS* s = reinterpret_cast<TS*>(l + n);                    // [n]
+  // two (a = D w, l = log(a/s)) pairs: the current point's and the line
+  // search's, swapped when a trial point is accepted; the Hessian build takes
+  // the trial pair's l for 1/a
+  TL* a = reinterpret_cast<TL*>(red + 8);                  // [n]
+  TL* l = a + n;                                           // [n]
+  TL* at = l + n;                                          // [n]
+  TL* lt = at + n;                                         // [n]
+  TS* s = reinterpret_cast<TS*>(lt + n);                   // [n]
   __shared__ int act[KMAX];
   __shared__ int ctl[4];
   __shared__ double wHs[KMAX];             // weights of the factor held in H
@@ -246,11 +261,12 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   const double hpen = p.pen == PEN_L2SQ ? p.alpha : (p.pen == PEN_EN ? p.beta : 0.0);
 
   int it = 0;
+  double f = 0.0;          // V(w); with a and l valid for w when have_f
+  bool have_f = false;
   for (; it < p.max_newton; ++it) {
-    const double f = pn_eval<MAXB>(p, DTp, ld_dt, n, k, w, s, a, red);  // also a = D w (block_sum synchronises)
+    if (!have_f) f = pn_eval<MAXB>(p, DTp, ld_dt, n, k, w, s, a, l, tiny, red);  // block_sum synchronises
+    have_f = true;
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
-    for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)log(fmax((double)a[i], tiny) / (double)s[i]);
-    __syncthreads();
     {
       // thread (j = lane + 64 cc, q = wave) sums bins i = q, q + 4, ... of column j;
       // eight independent partial sums keep the D loads in flight
@@ -264,9 +280,12 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
         if (j < k) {
           const float* dcol = Dp + j;
           int i = q;
-          for (; i + 28 < n; i += 32) {
+          for (; i + 60 < n; i += 64) {  // sixteen loads in flight
+            float dv[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) part[u] += (double)dcol[(size_t)(i + 4 * u) * ld_d] * (double)l[i + 4 * u];
+            for (int u = 0; u < 16; ++u) dv[u] = dcol[(size_t)(i + 4 * u) * ld_d];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) part[u & 7] += (double)dv[u] * (double)l[i + 4 * u];
           }
           for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * ld_d] * (double)l[i];
         }
@@ -333,41 +352,72 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
     __syncthreads();
     if (!ctl[3]) {
       // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
-      for (int i = tid; i < n; i += PN_THREADS) l[i] = (TL)(1.0 / fmax((double)a[i], tiny));
+      TL* ra = lt;  // 1 / a_i (the trial buffer is free until the line search)
+      for (int i = tid; i < n; i += PN_THREADS) ra[i] = (TL)(1.0 / fmax((double)a[i], tiny));
       __syncthreads();
-      if constexpr (KMAX == 64) {
-        // 128 register blocks of 8 x 4 entries (block row bj = 0..7, block column
-        // bl = 0..15) over two bin groups (bins of parity q)
-        const int q = tid >> 7, blk = tid & 127, bj = blk >> 4, bl = blk & 15;
-        double acc[8][4];
+      if constexpr (KMAX == 64 && sizeof(TH) == 8) {
+        // FP64 matrix cores: the 10 lower-triangle 16 x 16 blocks (p >= q) of the
+        // 4 x 4 block grid.  Wave w takes the 4-bin steps w, w + 4, ...; in a step
+        // lane l supplies bin 4 st + l/16 and column 16 p + l%16 of every panel p,
+        // as the A operand (scaled by 1 / a_i) and as the B operand.
+        f64x4 acc[10];
 #pragma unroll
-        for (int x = 0; x < 8; ++x)
+        for (int x = 0; x < 10; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int c16 = lane & 15, ks = lane >> 4;
+        const int nst = (n + 3) >> 2;
+        // operands of step st into registers (zero past the last bin)
+        auto load_step = [&](int st, float (&v)[4], double& sc) {
+          const int i = 4 * st + ks;
+          if (st < nst && i < n) {
+            const float* row = Dp + (size_t)i * ld_d + c16;
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        const float* rowj = Dp + bj * 8;
-        const float* rowl = Dp + bl * 4;
-        for (int i = q; i < n; i += 2) {
-          const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
-          const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
-          const float4 lv = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
-          const double sc = l[i];  // 1 / a_i
-          const double xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
-          const double xb[4] = {(double)lv.x, (double)lv.y, (double)lv.z, (double)lv.w};
+            for (int pp = 0; pp < 4; ++pp) v[pp] = row[16 * pp];
+            sc = (double)ra[i];
+          } else {
 #pragma unroll
-          for (int x = 0; x < 8; ++x)
+            for (int pp = 0; pp < 4; ++pp) v[pp] = 0.f;
+            sc = 0.0;
+          }
+        };
+        auto mfma_step = [&](const float (&v)[4], double sc) {
+          double bq[4], ap[4];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += xa[x] * xb[y];
+          for (int pp = 0; pp < 4; ++pp) {
+            bq[pp] = (double)v[pp];
+            ap[pp] = bq[pp] * sc;
+          }
+          int x = 0;
+#pragma unroll
+          for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+            for (int qq = 0; qq <= pp; ++qq, ++x)
+              acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
+        };
+        // two steps of loads in flight behind the matrix-core work
+        float v0[4], v1[4];
+        double s0, s1;
+        load_step(wave, v0, s0);
+        load_step(wave + 4, v1, s1);
+        for (int st = wave; st < nst; st += 8) {
+          mfma_step(v0, s0);
+          load_step(st + 8, v0, s0);
+          mfma_step(v1, s1);
+          load_step(st + 12, v1, s1);
         }
-        // fold the two bin groups into H
-        for (int grp = 0; grp < 2; ++grp) {
-          if (q == grp) {
+        // sum the four waves' partial blocks into H in wave order (lane l,
+        // register r holds block row l/16 + 4 r, block column l%16)
+        for (int src = 0; src < 4; ++src) {
+          if (wave == src) {
+            int x = 0;
 #pragma unroll
-            for (int x = 0; x < 8; ++x)
+            for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-              for (int y = 0; y < 4; ++y) {
-                TH* h = &H[(bj * 8 + x) * HLD + bl * 4 + y];
-                *h = (grp == 0 ? (TH)0 : *h) + (TH)acc[x][y];
-              }
+              for (int qq = 0; qq <= pp; ++qq, ++x)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  TH* h = &H[(16 * pp + ks + 4 * r) * HLD + 16 * qq + c16];
+                  *h = (src == 0 ? (TH)0 : *h) + (TH)acc[x][r];
+                }
           }
           __syncthreads();
         }
@@ -386,7 +436,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
           const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
           const float4 la = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
           const float4 lb = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d + 4);
-          const TH sc = (TH)l[i];  // 1 / a_i
+          const TH sc = (TH)ra[i];  // 1 / a_i
           const TH xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
           const TH xb[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
 #pragma unroll
@@ -403,6 +453,7 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       // scale, add the penalty curvature, and pin the active weights (identity rows)
       for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) {
         const int r = e / KMAX, c = e % KMAX;
+        if (c > r) continue;  // the factorisation and the solves read the lower triangle only
         double h = p.eps * (double)H[r * HLD + c];
         if (act[r] || act[c]) h = (r == c) ? 1.0 : 0.0;
         else if (r == c) h += hpen;
@@ -526,21 +577,29 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       slope = pn_block_sum(sl, red);
       tmax = pn_block_min(tm, red);
     }
-    bool accepted = false;
-    double t = fmin(1.0, tmax);
+    bool accepted = false, evaluated = false;
+    double t = fmin(1.0, tmax), fn = 0.0;
+    // trial point w + t d clipped at 0; at t = tmax the weights that stop the
+    // ratio test land exactly on 0 (they join the active set if it is accepted)
+    auto trial = [&](double tt) {
+      if (tid < KMAX) {
+        double v = act[tid] ? 0.0 : fmax(w[tid] + tt * d[tid], 0.0);
+        if (tt == tmax && !act[tid] && d[tid] < 0.0 && -w[tid] / d[tid] <= tmax * (1.0 + 1e-12)) v = 0.0;
+        wt[tid] = v;
+      }
+      __syncthreads();
+    };
     if (slope < 0.0 && -slope <= 1e-14 * fabs(f)) {
       // the predicted decrease is below what V can resolve in FP64: the point is
       // optimal to working precision on this free set, take the step untested
-      if (tid < KMAX) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
-      __syncthreads();
+      trial(t);
       accepted = true;
     } else if (slope < 0.0) {
       for (int ls = 0; ls < 30; ++ls) {
-        if (tid < KMAX) wt[tid] = act[tid] ? 0.0 : fmax(w[tid] + t * d[tid], 0.0);
-        __syncthreads();
-        const double fn = pn_eval<MAXB>(p, DTp, ld_dt, n, k, wt, s, (TL*)nullptr, red);
+        trial(t);
+        fn = pn_eval<MAXB>(p, DTp, ld_dt, n, k, wt, s, at, lt, tiny, red);
         if (fn <= f + 1e-4 * t * slope) {
-          accepted = true;
+          accepted = evaluated = true;
           break;
         }
         t *= 0.5;
@@ -562,15 +621,20 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
       }
       break;
     }
-    const bool hit = (t == tmax);
     if (tid < KMAX) {
-      double wn = wt[tid];
-      // the weights that stop the ratio test join the active set at exactly 0
-      if (hit && !act[tid] && d[tid] < 0.0 && -w[tid] / d[tid] <= tmax * (1.0 + 1e-12)) {
-        act[tid] = 1;
-        wn = 0.0;
-      }
-      w[tid] = wn;
+      if (t == tmax && !act[tid] && d[tid] < 0.0 && -w[tid] / d[tid] <= tmax * (1.0 + 1e-12)) act[tid] = 1;
+      w[tid] = wt[tid];
+    }
+    if (evaluated) {  // the accepted trial's a, l and V are the new point's
+      TL* x = a;
+      a = at;
+      at = x;
+      x = l;
+      l = lt;
+      lt = x;
+      f = fn;
+    } else {
+      have_f = false;
     }
     __syncthreads();
   }
@@ -592,10 +656,14 @@ __global__ __launch_bounds__(PN_THREADS) void prox_newton_kernel(ProxNewtonArgs<
   }
 }
 
+// Largest dynamic LDS of one workgroup (the 160 KB of a CU less the kernel's
+// static arrays, which take under 1 KB).
+constexpr size_t PN_LDS_MAX = 160 * 1024 - 1024;
+
 // Dynamic LDS of prox_newton_kernel<..., KMAX, TH> for n bins, s elements of
 // s_bytes and a / l elements of l_bytes.
 template <int KMAX = PN_K, class TH = double>
 inline size_t prox_newton_smem(int n, size_t s_bytes, size_t l_bytes = sizeof(double)) {
   return sizeof(TH) * (size_t)KMAX * (KMAX + 1) + sizeof(double) * (8 * (size_t)KMAX + 8) +
-         (2 * l_bytes + s_bytes) * (size_t)n;
+         (4 * l_bytes + s_bytes) * (size_t)n;
 }
