@@ -108,6 +108,37 @@ __device__ __forceinline__ void pn_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Value of v in lane `src` (wave-uniform) for every lane of the wave.
+__device__ __forceinline__ double pn_readlane(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Right-looking Cholesky of columns C0 .. C0 + 31 of the (already updated)
+// lower triangle of H in one wave, lane r holding row r's entries of those
+// columns; rows below the block are eliminated with it, so for C0 = 0 this
+// also yields the panel below the leading 32 x 32 block.  Each finished column
+// is stored at once; lanes above the diagonal store 0 into the unused upper
+// triangle, which keeps the code free of divergent branches.
+template <int C0>
+__device__ __forceinline__ void pn_chol_panel(double* H, int HLD, int lane) {
+  double h[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) h[j] = C0 + j <= lane ? H[lane * HLD + C0 + j] : 0.0;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) {
+    const double hcc = fmax(pn_readlane(h[c], C0 + c), 1e-300);
+    const double inv = rsqrt(hcc);  // 1 / L_cc
+    const double lrc = lane > C0 + c ? h[c] * inv : 0.0;
+    h[c] = lane == C0 + c ? hcc * inv : lrc;
+#pragma unroll
+    for (int q = c + 1; q < 32; ++q) h[q] -= lrc * pn_readlane(lrc, C0 + q);
+    H[lane * HLD + C0 + c] = h[c];
+  }
+}
+
 // penalty value alpha R(w) and derivatives, per weight
 __device__ __forceinline__ double pn_pen(int pen, double w, double alpha, double beta) {
   if (pen == PEN_L1) return alpha * w;
@@ -229,10 +260,9 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   __shared__ unsigned long long hmask_s[RPL];  // its active set
   __shared__ int hstate[2];               // [0] H holds a usable factor, [1] it was rebuilt here
   __shared__ double hrel_diag_s;          // Hessian diagonal entry of a released weight
-  __shared__ double kkt_s;                // free-set gradient of this iteration
   __shared__ int force_rebuild;           // the last reused factor gave no descent
-  double kkt_prev = 0.0;                  // (thread 0) the free gradient of the previous iteration
-  int last_reused = 0;                    // (thread 0) the previous step used a reused factor
+  double kkt_prev = 0.0;                  // (wave 0) the free gradient of the previous iteration
+  int last_reused = 0;                    // (wave 0) the previous step used a reused factor
   int nfac = 0;
 
   for (int i = tid; i < n; i += PN_THREADS) s[i] = srow[i];
@@ -298,58 +328,91 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
       }
       __syncthreads();
     }
-    // ---- optimality of the free set; release the most negative active gradient
-    if (tid == 0) {
+    // ---- optimality of the free set, release of the most negative active
+    // gradient, and whether the factor held in H serves this step: wave 0 by
+    // butterfly reductions, so every lane ends with the same values
+    if (wave == 0) {
       double kkt = 0.0, gmin = 0.0;
-      int jmin = -1;
-      for (int j = 0; j < k; ++j) {
-        if (!act[j]) kkt = fmax(kkt, fabs(g[j]));
-        else if (g[j] < gmin) {
-          gmin = g[j];
-          jmin = j;
+      int jmin = 0x7fffffff;  // (gmin, jmin): the smallest (g_j, j) over active j with g_j < 0
+#pragma unroll
+      for (int cc = 0; cc < RPL; ++cc) {
+        const int j = lane + 64 * cc;
+        if (j < k) {
+          const double gj = g[j];
+          if (!act[j]) {
+            kkt = fmax(kkt, fabs(gj));
+          } else if (gj < gmin) {
+            gmin = gj;
+            jmin = j;
+          }
         }
       }
-      int stop = 0, released = -1;
-      if (kkt <= gscale && !(jmin >= 0 && gmin < -gscale)) stop = 1;
-      else if (jmin >= 0 && gmin < -gscale && kkt <= fmax(gscale, 0.1 * fabs(gmin))) {
-        act[jmin] = 0;
-        released = jmin;
-        jmin = -1;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        kkt = fmax(kkt, __shfl_xor(kkt, off, 64));
+        const double og = __shfl_xor(gmin, off, 64);
+        const int oj = __shfl_xor(jmin, off, 64);
+        if (og < gmin || (og == gmin && oj < jmin)) {
+          gmin = og;
+          jmin = oj;
+        }
       }
-      ctl[0] = stop;
-      ctl[1] = released;
-      ctl[2] = (jmin >= 0 && gmin < -gscale) ? jmin : -1;   // release candidate if no descent is left
-      kkt_s = kkt;
+      const bool cand = jmin != 0x7fffffff && gmin < -gscale;
+      int stop = 0, rel = -1, next = cand ? jmin : -1;  // next: release candidate if no descent is left
+      if (kkt <= gscale && !cand) {
+        stop = 1;
+      } else if (cand && kkt <= fmax(gscale, 0.1 * fabs(gmin))) {
+        rel = jmin;
+        next = -1;
+      }
+      int reuse = 0;
+      unsigned long long mask[RPL];
+      if (!stop) {
+        bool same = true;
+#pragma unroll
+        for (int cc = 0; cc < RPL; ++cc) {
+          const int j = lane + 64 * cc;
+          mask[cc] = __ballot(j < k && act[j] && j != rel);
+          same = same && mask[cc] == hmask_s[cc];
+        }
+        // a step on a reused factor that did not halve the free gradient: refactor
+        const bool poor = (last_reused && kkt > 0.5 * kkt_prev) || force_rebuild;
+        if (hstate[0] && rel < 0 && same && !poor) {
+          double dm = 0.0, wm = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < RPL; ++cc) {
+            const int j = lane + 64 * cc;
+            if (j < k) {
+              dm = fmax(dm, fabs(w[j] - wHs[j]));
+              wm = fmax(wm, fabs(wHs[j]));
+            }
+          }
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            dm = fmax(dm, __shfl_xor(dm, off, 64));
+            wm = fmax(wm, __shfl_xor(wm, off, 64));
+          }
+          reuse = dm <= p.reuse_tol * wm;
+        }
+        last_reused = reuse;
+        kkt_prev = kkt;
+      }
+      if (lane == 0) {
+        ctl[0] = stop;
+        ctl[1] = rel;
+        ctl[2] = next;
+        ctl[3] = reuse;
+        if (!stop) {
+          if (rel >= 0) act[rel] = 0;
+          force_rebuild = 0;
+          if (!reuse)
+            for (int m = 0; m < RPL; ++m) hmask_s[m] = mask[m];
+        }
+      }
     }
     __syncthreads();
     if (ctl[0]) break;
     const int released = ctl[1];
-    if (tid == 0) {  // reuse the factor held in H?
-      unsigned long long mask[RPL];
-      for (int m = 0; m < RPL; ++m) mask[m] = 0ull;
-      for (int j = 0; j < k; ++j)
-        if (act[j]) mask[j >> 6] |= 1ull << (j & 63);
-      bool same = true;
-      for (int m = 0; m < RPL; ++m) same = same && mask[m] == hmask_s[m];
-      int reuse = 0;
-      // a step on a reused factor that did not halve the free gradient: refactor
-      const bool poor = (last_reused && kkt_s > 0.5 * kkt_prev) || force_rebuild;
-      force_rebuild = 0;
-      if (hstate[0] && released < 0 && same && !poor) {
-        double dm = 0.0, wm = 0.0;
-        for (int j = 0; j < k; ++j) {
-          dm = fmax(dm, fabs(w[j] - wHs[j]));
-          wm = fmax(wm, fabs(wHs[j]));
-        }
-        reuse = dm <= p.reuse_tol * wm;
-      }
-      ctl[3] = reuse;
-      if (!reuse)
-        for (int m = 0; m < RPL; ++m) hmask_s[m] = mask[m];
-      last_reused = reuse;
-      kkt_prev = kkt_s;
-    }
-    __syncthreads();
     if (!ctl[3]) {
       // ---- Hessian on the free set: H = eps D^T diag(1/a) D + hpen I
       TL* ra = lt;  // 1 / a_i (the trial buffer is free until the line search)
@@ -405,7 +468,8 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           load_step(st + 12, v1, s1);
         }
         // sum the four waves' partial blocks into H in wave order (lane l,
-        // register r holds block row l/16 + 4 r, block column l%16)
+        // register r holds block row l/16 + 4 r, block column l%16); the last
+        // pass applies the scaling and the active-set pins
         for (int src = 0; src < 4; ++src) {
           if (wave == src) {
             int x = 0;
@@ -415,8 +479,15 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
               for (int qq = 0; qq <= pp; ++qq, ++x)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                  TH* h = &H[(16 * pp + ks + 4 * r) * HLD + 16 * qq + c16];
-                  *h = (src == 0 ? (TH)0 : *h) + (TH)acc[x][r];
+                  const int row = 16 * pp + ks + 4 * r, col = 16 * qq + c16;
+                  TH* h = &H[row * HLD + col];
+                  double v = (src == 0 ? 0.0 : (double)*h) + acc[x][r];
+                  if (src == 3) {  // scale, penalty curvature, identity rows of the active weights
+                    v *= p.eps;
+                    if (act[row] || act[col]) v = (row == col) ? 1.0 : 0.0;
+                    else if (row == col) v += hpen;
+                  }
+                  *h = (TH)v;
                 }
           }
           __syncthreads();
@@ -450,66 +521,91 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           for (int y = 0; y < 8; ++y) H[(bj * 8 + x) * HLD + bl * 8 + y] = acc[x][y];
         __syncthreads();
       }
-      // scale, add the penalty curvature, and pin the active weights (identity rows)
-      for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) {
-        const int r = e / KMAX, c = e % KMAX;
-        if (c > r) continue;  // the factorisation and the solves read the lower triangle only
-        double h = p.eps * (double)H[r * HLD + c];
-        if (act[r] || act[c]) h = (r == c) ? 1.0 : 0.0;
-        else if (r == c) h += hpen;
-        H[r * HLD + c] = (TH)h;
-      }
-      __syncthreads();
-      if (tid == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
-      __syncthreads();
-
-      // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
-      // the diagonal tile in one wave, solve the panel below it (one thread per
-      // row), update the trailing lower triangle (all threads).
-      for (int kk = 0; kk < KMAX; kk += 16) {
-        if (wave == 0 && lane < 16) {
-          const int r = kk + lane;
-          TH* Hr = H + r * HLD;
-          for (int c = kk; c < kk + 16; ++c) {
-            TH acc = 0;
-            if (r >= c) {
-              const TH* Hc = H + c * HLD;
-              acc = Hr[c];
-              for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
-            }
-            if (r == c) Hr[c] = sqrt(acc > (TH)0 ? acc : tinyh);
-            pn_wave_sync();
-            if (r > c) Hr[c] = acc / H[c * HLD + c];
-            pn_wave_sync();
-          }
-        }
-        __syncthreads();
-        for (int r = kk + 16 + tid; r < KMAX; r += PN_THREADS) {
-          TH* Hr = H + r * HLD;
-          for (int c = kk; c < kk + 16; ++c) {
-            const TH* Hc = H + c * HLD;
-            TH acc = Hr[c];
-            for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
-            Hr[c] = acc / Hc[c];
-          }
-        }
-        __syncthreads();
-        const int m = KMAX - kk - 16;
-        for (int e = tid; e < m * m; e += PN_THREADS) {
-          const int r = kk + 16 + e / m, c = kk + 16 + e % m;
-          if (c <= r) {
-            const TH* Hr = H + r * HLD;
-            const TH* Hc = H + c * HLD;
-            TH s0 = 0, s1 = 0;
+      if constexpr (KMAX == 64) {
+        // ---- Cholesky H = L L^T (lower triangle in place) in wave 0, lane r
+        // holding row r: (1) columns 0..31 of every row, right-looking, (2) the
+        // Schur update of the trailing 32 x 32 block, (3) its factorisation.
+        // Column entries reach the other lanes by v_readlane; finished columns go
+        // straight back to LDS, so at most 32 entries per lane live in registers.
+        if (wave == 0) {
+          if (lane == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
+          pn_chol_panel<0>(H, HLD, lane);
+          double h[32];
 #pragma unroll
-            for (int q = 0; q < 16; q += 2) {
-              s0 += Hr[kk + q] * Hc[kk + q];
-              s1 += Hr[kk + q + 1] * Hc[kk + q + 1];
-            }
-            H[r * HLD + c] -= s0 + s1;
+          for (int j = 0; j < 32; ++j) h[j] = 32 + j <= lane ? (double)H[lane * HLD + 32 + j] : 0.0;
+#pragma unroll
+          for (int c = 0; c < 32; ++c) {
+            const double v = H[lane * HLD + c];  // L_rc
+#pragma unroll
+            for (int j = 0; j < 32; ++j) h[j] -= v * pn_readlane(v, 32 + j);
           }
+#pragma unroll
+          for (int j = 0; j < 32; ++j) H[lane * HLD + 32 + j] = h[j];
+          pn_chol_panel<32>(H, HLD, lane);
         }
         __syncthreads();
+      } else {
+        // scale, add the penalty curvature, and pin the active weights (identity rows)
+        for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) {
+          const int r = e / KMAX, c = e % KMAX;
+          if (c > r) continue;  // the factorisation and the solves read the lower triangle only
+          double h = p.eps * (double)H[r * HLD + c];
+          if (act[r] || act[c]) h = (r == c) ? 1.0 : 0.0;
+          else if (r == c) h += hpen;
+          H[r * HLD + c] = (TH)h;
+        }
+        __syncthreads();
+        if (tid == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
+        __syncthreads();
+
+        // ---- Cholesky H = L L^T (lower triangle in place) by 16 x 16 tiles: factor
+        // the diagonal tile in one wave, solve the panel below it (one thread per
+        // row), update the trailing lower triangle (all threads).
+        for (int kk = 0; kk < KMAX; kk += 16) {
+          if (wave == 0 && lane < 16) {
+            const int r = kk + lane;
+            TH* Hr = H + r * HLD;
+            for (int c = kk; c < kk + 16; ++c) {
+              TH acc = 0;
+              if (r >= c) {
+                const TH* Hc = H + c * HLD;
+                acc = Hr[c];
+                for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
+              }
+              if (r == c) Hr[c] = sqrt(acc > (TH)0 ? acc : tinyh);
+              pn_wave_sync();
+              if (r > c) Hr[c] = acc / H[c * HLD + c];
+              pn_wave_sync();
+            }
+          }
+          __syncthreads();
+          for (int r = kk + 16 + tid; r < KMAX; r += PN_THREADS) {
+            TH* Hr = H + r * HLD;
+            for (int c = kk; c < kk + 16; ++c) {
+              const TH* Hc = H + c * HLD;
+              TH acc = Hr[c];
+              for (int q = kk; q < c; ++q) acc -= Hr[q] * Hc[q];
+              Hr[c] = acc / Hc[c];
+            }
+          }
+          __syncthreads();
+          const int m = KMAX - kk - 16;
+          for (int e = tid; e < m * m; e += PN_THREADS) {
+            const int r = kk + 16 + e / m, c = kk + 16 + e % m;
+            if (c <= r) {
+              const TH* Hr = H + r * HLD;
+              const TH* Hc = H + c * HLD;
+              TH s0 = 0, s1 = 0;
+  #pragma unroll
+              for (int q = 0; q < 16; q += 2) {
+                s0 += Hr[kk + q] * Hc[kk + q];
+                s1 += Hr[kk + q + 1] * Hc[kk + q + 1];
+              }
+              H[r * HLD + c] -= s0 + s1;
+            }
+          }
+          __syncthreads();
+        }
       }
       if (tid < KMAX) wHs[tid] = w[tid];
       if (tid == 0) {
@@ -530,22 +626,55 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         const int r = lane + 64 * rr;
         y[rr] = act[r] ? 0.0 : -g[r];
       }
-      for (int c = 0; c < KMAX; ++c) {
-        const double yc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+      if constexpr (KMAX == 64) {
+        // lane r keeps row r of L (forward), then column r (backward), in
+        // registers; y_c and 1 / L_cc reach the other lanes by v_readlane
+        const int r = lane;
+        const double inv_r = 1.0 / (double)H[r * HLD + r];
+        double yv = y[0];
 #pragma unroll
-        for (int rr = 0; rr < RPL; ++rr) {
-          const int r = lane + 64 * rr;
-          if (r == c) y[rr] = yc;
-          else if (r > c) y[rr] -= (double)H[r * HLD + c] * yc;
+        for (int cb = 0; cb < 64; cb += 16) {  // L entries 16 at a time (bounded registers)
+          double lr[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) lr[u] = cb + u < r ? (double)H[r * HLD + cb + u] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const double yc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
+            yv = r == cb + u ? yc : yv - lr[u] * yc;
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
-      }
-      for (int c = KMAX - 1; c >= 0; --c) {
-        const double dc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
 #pragma unroll
-        for (int rr = 0; rr < RPL; ++rr) {
-          const int r = lane + 64 * rr;
-          if (r == c) y[rr] = dc;
-          else if (r < c) y[rr] -= (double)H[c * HLD + r] * dc;
+        for (int cb = 48; cb >= 0; cb -= 16) {
+          double lc[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) lc[u] = cb + u > r ? (double)H[(cb + u) * HLD + r] : 0.0;
+#pragma unroll
+          for (int u = 15; u >= 0; --u) {
+            const double dc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
+            yv = r == cb + u ? dc : yv - lc[u] * dc;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        y[0] = yv;
+      } else {
+        for (int c = 0; c < KMAX; ++c) {
+          const double yc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + 64 * rr;
+            if (r == c) y[rr] = yc;
+            else if (r > c) y[rr] -= (double)H[r * HLD + c] * yc;
+          }
+        }
+        for (int c = KMAX - 1; c >= 0; --c) {
+          const double dc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) {
+            const int r = lane + 64 * rr;
+            if (r == c) y[rr] = dc;
+            else if (r < c) y[rr] -= (double)H[c * HLD + r] * dc;
+          }
         }
       }
       // weights at 0 cannot decrease; a released weight swamped by the coupling
