@@ -108,6 +108,20 @@ __device__ __forceinline__ void pn_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Buffer resource over nfloats floats at p (raw, unswizzled; word 3 as CDNA
+// expects).  Loads through it take one 32-bit lane offset and a wave-uniform
+// offset instead of a 64-bit address per lane, so many can be in flight.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pn_rsrc(const float* p, long long nfloats) {
+  const long long bytes = nfloats * 4;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0,
+                                           (int)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL), 0x00020000);
+}
+// p[(voff + soff) / 4] with voff per lane and soff wave-uniform (bytes); every
+// caller keeps voff + soff inside the buffer.
+__device__ __forceinline__ float pn_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // Value of v in lane `src` (wave-uniform) for every lane of the wave.
 __device__ __forceinline__ double pn_readlane(double v, int src) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -116,27 +130,59 @@ __device__ __forceinline__ double pn_readlane(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Right-looking Cholesky of columns C0 .. C0 + 31 of the (already updated)
-// lower triangle of H in one wave, lane r holding row r's entries of those
-// columns; rows below the block are eliminated with it, so for C0 = 0 this
-// also yields the panel below the leading 32 x 32 block.  Each finished column
-// is stored at once; lanes above the diagonal store 0 into the unused upper
-// triangle, which keeps the code free of divergent branches.
+// Right-looking Cholesky of the 16 columns C0 .. C0 + 15 of the (already
+// updated) lower triangle of a 64 x 64 matrix H in LDS, in one wave: lane r
+// holds row r's entries of those columns, column entries reach the other
+// lanes by v_readlane, and the rows below the block are eliminated with it
+// (the panel of L under the diagonal block).  Each finished column is stored
+// at once; lanes above the diagonal store 0 into the unused upper triangle,
+// which keeps the code free of divergent branches.
 template <int C0>
 __device__ __forceinline__ void pn_chol_panel(double* H, int HLD, int lane) {
-  double h[32];
+  double h[16];
 #pragma unroll
-  for (int j = 0; j < 32; ++j) h[j] = C0 + j <= lane ? H[lane * HLD + C0 + j] : 0.0;
+  for (int j = 0; j < 16; ++j) h[j] = C0 + j <= lane ? H[lane * HLD + C0 + j] : 0.0;
 #pragma unroll
-  for (int c = 0; c < 32; ++c) {
+  for (int c = 0; c < 16; ++c) {
     const double hcc = fmax(pn_readlane(h[c], C0 + c), 1e-300);
     const double inv = rsqrt(hcc);  // 1 / L_cc
     const double lrc = lane > C0 + c ? h[c] * inv : 0.0;
     h[c] = lane == C0 + c ? hcc * inv : lrc;
 #pragma unroll
-    for (int q = c + 1; q < 32; ++q) h[q] -= lrc * pn_readlane(lrc, C0 + q);
+    for (int q = c + 1; q < 16; ++q) h[q] -= lrc * pn_readlane(lrc, C0 + q);
     H[lane * HLD + C0 + c] = h[c];
   }
+}
+
+// Schur update of the trailing lower triangle of that matrix after the panel
+// at columns R0 - 16 .. R0 - 1:  H[i][j] -= sum_c L[i][c] L[j][c]  for
+// R0 <= j <= i < 64, on the FP64 matrix cores (16 x 16 blocks, 4 columns of
+// the panel per step), in one wave.
+template <int R0>
+__device__ __forceinline__ void pn_chol_schur(double* H, int HLD, int lane) {
+  constexpr int NB = (64 - R0) / 16, NBLK = NB * (NB + 1) / 2, C0 = R0 - 16;
+  const int c16 = lane & 15, ks = lane >> 4;
+  f64x4 acc[NBLK];
+#pragma unroll
+  for (int x = 0; x < NBLK; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c0 = 0; c0 < 16; c0 += 4) {
+    double xv[NB];  // L[R0 + 16 bi + lane%16][C0 + c0 + lane/16]: A and B operands alike
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) xv[bi] = H[(R0 + 16 * bi + c16) * HLD + C0 + c0 + ks];
+    int x = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj <= bi; ++bj, ++x) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[bi], xv[bj], acc[x], 0, 0, 0);
+  }
+  int x = 0;
+#pragma unroll
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj <= bi; ++bj, ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) H[(R0 + 16 * bi + ks + 4 * r) * HLD + R0 + 16 * bj + c16] -= acc[x][r];
 }
 
 // penalty value alpha R(w) and derivatives, per weight
@@ -161,20 +207,23 @@ template <int MAXB, class TS, class TW, class TL>
 __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int ld_dt, int n, int k,
                           const double* w, const TS* s, TL* a, TL* l, double tiny, double* red) {
   double ai[MAXB];
+  int vo[MAXB];  // byte offsets of this thread's bins in a row of D^T, clamped into the row
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) ai[q] = 0.0;
-  const float* base = DTp + threadIdx.x;
-  const int nq = (n - (int)threadIdx.x + PN_THREADS - 1) / PN_THREADS;  // bins of this thread
+  for (int q = 0; q < MAXB; ++q) {
+    ai[q] = 0.0;
+    vo[q] = min((int)threadIdx.x + q * PN_THREADS, n - 1) * 4;
+  }
+  const __amdgpu_buffer_rsrc_t rs = pn_rsrc(DTp, (long long)k * ld_dt);
+  constexpr int CW = MAXB <= 4 ? 16 : 8;  // columns per step: CW * MAXB independent loads in flight
   int j = 0;
-  for (; j + 7 < k; j += 8) {  // eight columns per step: up to 32 independent loads in flight
-    float dv[8][MAXB];
+  for (; j + CW <= k; j += CW) {
+    float dv[CW][MAXB];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < CW; ++u)
 #pragma unroll
-      for (int q = 0; q < MAXB; ++q)
-        dv[u][q] = q < nq ? base[(size_t)(j + u) * ld_dt + q * PN_THREADS] : 0.f;
+      for (int q = 0; q < MAXB; ++q) dv[u][q] = pn_ld(rs, vo[q], (j + u) * ld_dt * 4);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < CW; ++u) {
       const double wj = w[j + u];
 #pragma unroll
       for (int q = 0; q < MAXB; ++q) ai[q] += (double)dv[u][q] * wj;
@@ -183,8 +232,7 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int
   for (; j < k; ++j) {
     const double wj = w[j];
 #pragma unroll
-    for (int q = 0; q < MAXB; ++q)
-      if (q < nq) ai[q] += (double)base[(size_t)j * ld_dt + q * PN_THREADS] * wj;
+    for (int q = 0; q < MAXB; ++q) ai[q] += (double)pn_ld(rs, vo[q], j * ld_dt * 4) * wj;
   }
   double acc = 0.0;
 #pragma unroll
@@ -198,10 +246,9 @@ __device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int
       acc += (ai[q] > 0.0 ? ai[q] * lg : 0.0) - ai[q] + si;
     }
   }
-  double v = p.eps * pn_block_sum(acc, red);
-  double pv = 0.0;
-  for (int j = 0; j < k; ++j) pv += pn_pen(p.pen, w[j], p.alpha, p.beta);
-  return v + pv;
+  acc *= p.eps;
+  if ((int)threadIdx.x < k) acc += pn_pen(p.pen, w[threadIdx.x], p.alpha, p.beta);
+  return pn_block_sum(acc, red);
 }
 
 // Template parameters: MAXB bins per thread (n <= 256 MAXB); TL storage of a
@@ -308,16 +355,17 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
 #pragma unroll
         for (int u = 0; u < 8; ++u) part[u] = 0.0;
         if (j < k) {
-          const float* dcol = Dp + j;
-          int i = q;
+          const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
+          const int vj = j * 4;
+          int i = __builtin_amdgcn_readfirstlane(q);
           for (; i + 60 < n; i += 64) {  // sixteen loads in flight
             float dv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) dv[u] = dcol[(size_t)(i + 4 * u) * ld_d];
+            for (int u = 0; u < 16; ++u) dv[u] = pn_ld(rd, vj, (i + 4 * u) * ld_d * 4);
 #pragma unroll
             for (int u = 0; u < 16; ++u) part[u & 7] += (double)dv[u] * (double)l[i + 4 * u];
           }
-          for (; i < n; i += 4) part[0] += (double)dcol[(size_t)i * ld_d] * (double)l[i];
+          for (; i < n; i += 4) part[0] += (double)pn_ld(rd, vj, i * ld_d * 4) * (double)l[i];
         }
         gp[q * KMAX + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
       }
@@ -429,18 +477,14 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         const int c16 = lane & 15, ks = lane >> 4;
         const int nst = (n + 3) >> 2;
         // operands of step st into registers (zero past the last bin)
+        const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
         auto load_step = [&](int st, float (&v)[4], double& sc) {
           const int i = 4 * st + ks;
-          if (st < nst && i < n) {
-            const float* row = Dp + (size_t)i * ld_d + c16;
+          const bool in = i < n;  // (st < nst for every in-range bin)
+          const int vo = (min(i, n - 1) * ld_d + c16) * 4;
 #pragma unroll
-            for (int pp = 0; pp < 4; ++pp) v[pp] = row[16 * pp];
-            sc = (double)ra[i];
-          } else {
-#pragma unroll
-            for (int pp = 0; pp < 4; ++pp) v[pp] = 0.f;
-            sc = 0.0;
-          }
+          for (int pp = 0; pp < 4; ++pp) v[pp] = in ? pn_ld(rd, vo, 64 * pp) : 0.f;
+          sc = in ? (double)ra[min(i, n - 1)] : 0.0;
         };
         auto mfma_step = [&](const float (&v)[4], double sc) {
           double bq[4], ap[4];
@@ -522,26 +566,24 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         __syncthreads();
       }
       if constexpr (KMAX == 64) {
-        // ---- Cholesky H = L L^T (lower triangle in place) in wave 0, lane r
-        // holding row r: (1) columns 0..31 of every row, right-looking, (2) the
-        // Schur update of the trailing 32 x 32 block, (3) its factorisation.
-        // Column entries reach the other lanes by v_readlane; finished columns go
-        // straight back to LDS, so at most 32 entries per lane live in registers.
+        // ---- Cholesky H = L L^T (lower triangle in place) in wave 0: four
+        // 16-column panels in registers, each followed by the Schur update of
+        // the trailing lower triangle on the matrix cores
         if (wave == 0) {
           if (lane == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
           pn_chol_panel<0>(H, HLD, lane);
-          double h[32];
-#pragma unroll
-          for (int j = 0; j < 32; ++j) h[j] = 32 + j <= lane ? (double)H[lane * HLD + 32 + j] : 0.0;
-#pragma unroll
-          for (int c = 0; c < 32; ++c) {
-            const double v = H[lane * HLD + c];  // L_rc
-#pragma unroll
-            for (int j = 0; j < 32; ++j) h[j] -= v * pn_readlane(v, 32 + j);
-          }
-#pragma unroll
-          for (int j = 0; j < 32; ++j) H[lane * HLD + 32 + j] = h[j];
+          pn_wave_sync();
+          pn_chol_schur<16>(H, HLD, lane);
+          pn_wave_sync();
+          pn_chol_panel<16>(H, HLD, lane);
+          pn_wave_sync();
+          pn_chol_schur<32>(H, HLD, lane);
+          pn_wave_sync();
           pn_chol_panel<32>(H, HLD, lane);
+          pn_wave_sync();
+          pn_chol_schur<48>(H, HLD, lane);
+          pn_wave_sync();
+          pn_chol_panel<48>(H, HLD, lane);
         }
         __syncthreads();
       } else {
