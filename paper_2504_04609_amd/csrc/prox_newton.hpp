@@ -40,6 +40,7 @@
 // gradient; otherwise it builds and factors the Hessian anew.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include "gemm_nt_f64.hpp"
 #include "solver_kernels.hpp"
 
@@ -156,12 +157,14 @@ __device__ __forceinline__ void pn_chol_panel(double* H, int HLD, int lane) {
 
 // Schur update of the trailing lower triangle of that matrix after the panel
 // at columns R0 - 16 .. R0 - 1:  H[i][j] -= sum_c L[i][c] L[j][c]  for
-// R0 <= j <= i < 64, on the FP64 matrix cores (16 x 16 blocks, 4 columns of
-// the panel per step), in one wave.
+// R0 <= j <= i < R0 + 16 nb (nb <= (64 - R0) / 16 block rows, wave-uniform),
+// on the FP64 matrix cores (16 x 16 blocks, 4 columns of the panel per
+// step), in one wave.
 template <int R0>
-__device__ __forceinline__ void pn_chol_schur(double* H, int HLD, int lane) {
+__device__ __forceinline__ void pn_chol_schur(double* H, int HLD, int lane, int nb) {
   constexpr int NB = (64 - R0) / 16, NBLK = NB * (NB + 1) / 2, C0 = R0 - 16;
   const int c16 = lane & 15, ks = lane >> 4;
+  nb = __builtin_amdgcn_readfirstlane(nb);
   f64x4 acc[NBLK];
 #pragma unroll
   for (int x = 0; x < NBLK; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -169,20 +172,22 @@ __device__ __forceinline__ void pn_chol_schur(double* H, int HLD, int lane) {
   for (int c0 = 0; c0 < 16; c0 += 4) {
     double xv[NB];  // L[R0 + 16 bi + lane%16][C0 + c0 + lane/16]: A and B operands alike
 #pragma unroll
-    for (int bi = 0; bi < NB; ++bi) xv[bi] = H[(R0 + 16 * bi + c16) * HLD + C0 + c0 + ks];
+    for (int bi = 0; bi < NB; ++bi) xv[bi] = bi < nb ? H[(R0 + 16 * bi + c16) * HLD + C0 + c0 + ks] : 0.0;
     int x = 0;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-      for (int bj = 0; bj <= bi; ++bj, ++x) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[bi], xv[bj], acc[x], 0, 0, 0);
+      for (int bj = 0; bj <= bi; ++bj, ++x)
+        if (bi < nb) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[bi], xv[bj], acc[x], 0, 0, 0);
   }
   int x = 0;
 #pragma unroll
   for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
     for (int bj = 0; bj <= bi; ++bj, ++x)
+      if (bi < nb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) H[(R0 + 16 * bi + ks + 4 * r) * HLD + R0 + 16 * bj + c16] -= acc[x][r];
+        for (int r = 0; r < 4; ++r) H[(R0 + 16 * bi + ks + 4 * r) * HLD + R0 + 16 * bj + c16] -= acc[x][r];
 }
 
 // penalty value alpha R(w) and derivatives, per weight
@@ -302,6 +307,8 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   TL* lt = at + n;                                         // [n]
   TS* s = reinterpret_cast<TS*>(lt + n);                   // [n]
   __shared__ int act[KMAX];
+  __shared__ int perm[KMAX];  // 64-wide: the free weights in increasing order (compact positions)
+  __shared__ int cmp_s[2];    // [0] number of free weights m, [1] compact position of a released weight
   __shared__ int ctl[4];
   __shared__ double wHs[KMAX];             // weights of the factor held in H
   __shared__ unsigned long long hmask_s[RPL];  // its active set
@@ -445,6 +452,16 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         last_reused = reuse;
         kkt_prev = kkt;
       }
+      if constexpr (KMAX == 64) {  // compact positions of the free weights (after the release)
+        if (!stop) {
+          const bool fr = lane < k && (!act[lane] || lane == rel);
+          const unsigned long long fm = __ballot(fr);
+          const int x = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+          if (fr) perm[x] = lane;
+          if (lane == rel) cmp_s[1] = x;
+          if (lane == 0) cmp_s[0] = __popcll(fm);
+        }
+      }
       if (lane == 0) {
         ctl[0] = stop;
         ctl[1] = rel;
@@ -467,74 +484,91 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
       for (int i = tid; i < n; i += PN_THREADS) ra[i] = (TL)(1.0 / fmax((double)a[i], tiny));
       __syncthreads();
       if constexpr (KMAX == 64 && sizeof(TH) == 8) {
-        // FP64 matrix cores: the 10 lower-triangle 16 x 16 blocks (p >= q) of the
-        // 4 x 4 block grid.  Wave w takes the 4-bin steps w, w + 4, ...; in a step
-        // lane l supplies bin 4 st + l/16 and column 16 p + l%16 of every panel p,
-        // as the A operand (scaled by 1 / a_i) and as the B operand.
-        f64x4 acc[10];
-#pragma unroll
-        for (int x = 0; x < 10; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // FP64 matrix cores on the free weights only, in compact order: with m
+        // free weights and NP = ceil(m / 16) panels, the NP (NP + 1) / 2 lower
+        // 16 x 16 blocks (p >= q).  Wave w takes the 4-bin steps w, w + 4, ...;
+        // in a step lane l supplies bin 4 st + l/16 and the column of the free
+        // weight at compact position 16 p + l%16 of every panel p, as the A
+        // operand (scaled by 1 / a_i) and as the B operand.
+        const int m = cmp_s[0];
         const int c16 = lane & 15, ks = lane >> 4;
         const int nst = (n + 3) >> 2;
-        // operands of step st into registers (zero past the last bin)
         const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
-        auto load_step = [&](int st, float (&v)[4], double& sc) {
-          const int i = 4 * st + ks;
-          const bool in = i < n;  // (st < nst for every in-range bin)
-          const int vo = (min(i, n - 1) * ld_d + c16) * 4;
+        int colb[4];  // byte offset of this lane's column in each panel (-1: padding)
 #pragma unroll
-          for (int pp = 0; pp < 4; ++pp) v[pp] = in ? pn_ld(rd, vo, 64 * pp) : 0.f;
-          sc = in ? (double)ra[min(i, n - 1)] : 0.0;
-        };
-        auto mfma_step = [&](const float (&v)[4], double sc) {
-          double bq[4], ap[4];
+        for (int pp = 0; pp < 4; ++pp) colb[pp] = 16 * pp + c16 < m ? perm[16 * pp + c16] * 4 : -1;
+        auto hessian = [&](auto np_c) {
+          constexpr int NP = decltype(np_c)::value, NBLK = NP * (NP + 1) / 2;
+          f64x4 acc[NBLK];
 #pragma unroll
-          for (int pp = 0; pp < 4; ++pp) {
-            bq[pp] = (double)v[pp];
-            ap[pp] = bq[pp] * sc;
-          }
-          int x = 0;
+          for (int x = 0; x < NBLK; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
+          // operands of step st into registers (zero past the last bin and in padding)
+          auto load_step = [&](int st, float (&v)[NP], double& sc) {
+            const int i = 4 * st + ks;
+            const bool in = i < n;  // (st < nst for every in-range bin)
+            const int ro = min(i, n - 1) * ld_d * 4;
 #pragma unroll
-          for (int pp = 0; pp < 4; ++pp)
+            for (int pp = 0; pp < NP; ++pp) v[pp] = (in && colb[pp] >= 0) ? pn_ld(rd, ro + max(colb[pp], 0), 0) : 0.f;
+            sc = in ? (double)ra[min(i, n - 1)] : 0.0;
+          };
+          auto mfma_step = [&](const float (&v)[NP], double sc) {
+            double bq[NP], ap[NP];
 #pragma unroll
-            for (int qq = 0; qq <= pp; ++qq, ++x)
-              acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
-        };
-        // two steps of loads in flight behind the matrix-core work
-        float v0[4], v1[4];
-        double s0, s1;
-        load_step(wave, v0, s0);
-        load_step(wave + 4, v1, s1);
-        for (int st = wave; st < nst; st += 8) {
-          mfma_step(v0, s0);
-          load_step(st + 8, v0, s0);
-          mfma_step(v1, s1);
-          load_step(st + 12, v1, s1);
-        }
-        // sum the four waves' partial blocks into H in wave order (lane l,
-        // register r holds block row l/16 + 4 r, block column l%16); the last
-        // pass applies the scaling and the active-set pins
-        for (int src = 0; src < 4; ++src) {
-          if (wave == src) {
+            for (int pp = 0; pp < NP; ++pp) {
+              bq[pp] = (double)v[pp];
+              ap[pp] = bq[pp] * sc;
+            }
             int x = 0;
 #pragma unroll
-            for (int pp = 0; pp < 4; ++pp)
+            for (int pp = 0; pp < NP; ++pp)
 #pragma unroll
               for (int qq = 0; qq <= pp; ++qq, ++x)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int row = 16 * pp + ks + 4 * r, col = 16 * qq + c16;
-                  TH* h = &H[row * HLD + col];
-                  double v = (src == 0 ? 0.0 : (double)*h) + acc[x][r];
-                  if (src == 3) {  // scale, penalty curvature, identity rows of the active weights
-                    v *= p.eps;
-                    if (act[row] || act[col]) v = (row == col) ? 1.0 : 0.0;
-                    else if (row == col) v += hpen;
-                  }
-                  *h = (TH)v;
-                }
+                acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
+          };
+          // two steps of loads in flight behind the matrix-core work
+          float v0[NP], v1[NP];
+          double s0, s1;
+          load_step(wave, v0, s0);
+          load_step(wave + 4, v1, s1);
+          for (int st = wave; st < nst; st += 8) {
+            mfma_step(v0, s0);
+            load_step(st + 8, v0, s0);
+            mfma_step(v1, s1);
+            load_step(st + 12, v1, s1);
           }
-          __syncthreads();
+          // sum the four waves' partial blocks into H in wave order (lane l,
+          // register r holds block row l/16 + 4 r, block column l%16); the last
+          // pass scales, adds the penalty curvature and makes the padding
+          // positions m .. 16 NP - 1 identity rows
+          for (int src = 0; src < 4; ++src) {
+            if (wave == src) {
+              int x = 0;
+#pragma unroll
+              for (int pp = 0; pp < NP; ++pp)
+#pragma unroll
+                for (int qq = 0; qq <= pp; ++qq, ++x)
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * pp + ks + 4 * r, col = 16 * qq + c16;
+                    TH* h = &H[row * HLD + col];
+                    double v = (src == 0 ? 0.0 : (double)*h) + acc[x][r];
+                    if (src == 3) {
+                      v *= p.eps;
+                      if (row >= m || col >= m) v = (row == col) ? 1.0 : 0.0;
+                      else if (row == col) v += hpen;
+                    }
+                    *h = (TH)v;
+                  }
+            }
+            __syncthreads();
+          }
+        };
+        switch ((m + 15) >> 4) {
+          case 0:
+          case 1: hessian(std::integral_constant<int, 1>{}); break;
+          case 2: hessian(std::integral_constant<int, 2>{}); break;
+          case 3: hessian(std::integral_constant<int, 3>{}); break;
+          default: hessian(std::integral_constant<int, 4>{}); break;
         }
       } else {
         // 256 register blocks of 8 x 8 entries (block row bj, block column bl = 0..15)
@@ -566,24 +600,33 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         __syncthreads();
       }
       if constexpr (KMAX == 64) {
-        // ---- Cholesky H = L L^T (lower triangle in place) in wave 0: four
-        // 16-column panels in registers, each followed by the Schur update of
-        // the trailing lower triangle on the matrix cores
+        // ---- Cholesky H = L L^T of the compact 16 NP x 16 NP matrix (lower
+        // triangle in place) in wave 0: 16-column panels in registers, each
+        // followed by the Schur update of the trailing lower triangle on the
+        // matrix cores.  Rows past 16 NP hold stale values; they are eliminated
+        // along (in their own lanes) but never read.
         if (wave == 0) {
-          if (lane == 0) hrel_diag_s = released >= 0 ? (double)H[released * HLD + released] : 1.0;
+          const int np16 = __builtin_amdgcn_readfirstlane(max((cmp_s[0] + 15) >> 4, 1));
+          if (lane == 0) hrel_diag_s = released >= 0 ? (double)H[cmp_s[1] * HLD + cmp_s[1]] : 1.0;
           pn_chol_panel<0>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_schur<16>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_panel<16>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_schur<32>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_panel<32>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_schur<48>(H, HLD, lane);
-          pn_wave_sync();
-          pn_chol_panel<48>(H, HLD, lane);
+          if (np16 > 1) {
+            pn_wave_sync();
+            pn_chol_schur<16>(H, HLD, lane, np16 - 1);
+            pn_wave_sync();
+            pn_chol_panel<16>(H, HLD, lane);
+            if (np16 > 2) {
+              pn_wave_sync();
+              pn_chol_schur<32>(H, HLD, lane, np16 - 2);
+              pn_wave_sync();
+              pn_chol_panel<32>(H, HLD, lane);
+              if (np16 > 3) {
+                pn_wave_sync();
+                pn_chol_schur<48>(H, HLD, lane, 1);
+                pn_wave_sync();
+                pn_chol_panel<48>(H, HLD, lane);
+              }
+            }
+          }
         }
         __syncthreads();
       } else {
@@ -659,47 +702,63 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     }
     const double hdiag_released = released >= 0 ? hrel_diag_s : 1.0;
 
-    // ---- solve L L^T d = -g in wave 0 (lane owns rows lane + 64 rr)
+    // ---- solve L L^T d = -g in wave 0
     if (wave == 0) {
-      // forward: L y = -g ; backward: L^T d = y   (active rows: g = 0, L row = e_r)
-      double y[RPL];
-#pragma unroll
-      for (int rr = 0; rr < RPL; ++rr) {
-        const int r = lane + 64 * rr;
-        y[rr] = act[r] ? 0.0 : -g[r];
-      }
       if constexpr (KMAX == 64) {
-        // lane r keeps row r of L (forward), then column r (backward), in
-        // registers; y_c and 1 / L_cc reach the other lanes by v_readlane
-        const int r = lane;
-        const double inv_r = 1.0 / (double)H[r * HLD + r];
-        double yv = y[0];
+        // compact positions: lane x works on the free weight perm[x] (x < m);
+        // lane x keeps row x of L (forward), then column x (backward), 16
+        // entries at a time in registers; y_c and 1 / L_cc reach the other
+        // lanes by v_readlane
+        const int m = cmp_s[0];
+        const int nrow = __builtin_amdgcn_readfirstlane(max((m + 15) >> 4, 1)) * 16;
+        const int x = lane;
+        const int jx = x < m ? perm[x] : 0;
+        const double inv_r = 1.0 / (double)H[x * HLD + x];
+        double yv = x < m ? -g[jx] : 0.0;
 #pragma unroll
-        for (int cb = 0; cb < 64; cb += 16) {  // L entries 16 at a time (bounded registers)
-          double lr[16];
+        for (int cb = 0; cb < 64; cb += 16) {
+          if (cb < nrow) {
+            double lr[16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) lr[u] = cb + u < r ? (double)H[r * HLD + cb + u] : 0.0;
+            for (int u = 0; u < 16; ++u) lr[u] = cb + u < x ? (double)H[x * HLD + cb + u] : 0.0;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const double yc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
-            yv = r == cb + u ? yc : yv - lr[u] * yc;
+            for (int u = 0; u < 16; ++u) {
+              const double yc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
+              yv = x == cb + u ? yc : yv - lr[u] * yc;
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int cb = 48; cb >= 0; cb -= 16) {
-          double lc[16];
+          if (cb < nrow) {
+            double lc[16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) lc[u] = cb + u > r ? (double)H[(cb + u) * HLD + r] : 0.0;
+            for (int u = 0; u < 16; ++u) lc[u] = cb + u > x ? (double)H[(cb + u) * HLD + x] : 0.0;
 #pragma unroll
-          for (int u = 15; u >= 0; --u) {
-            const double dc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
-            yv = r == cb + u ? dc : yv - lc[u] * dc;
+            for (int u = 15; u >= 0; --u) {
+              const double dc = pn_readlane(yv, cb + u) * pn_readlane(inv_r, cb + u);
+              yv = x == cb + u ? dc : yv - lc[u] * dc;
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        y[0] = yv;
+        // weights at 0 cannot decrease; a released weight swamped by the coupling
+        // takes its own Newton coordinate step instead
+        if (x < m && w[jx] <= 0.0 && yv < 0.0) yv = 0.0;
+        const double yr = __shfl(yv, released >= 0 ? cmp_s[1] : 0, 64);
+        if (released >= 0 && yr <= 0.0) yv = (x < m && jx == released) ? -g[jx] / hdiag_released : 0.0;
+        if (act[lane]) d[lane] = 0.0;
+        if (x < m) d[jx] = yv;
       } else {
+        // lane owns rows lane + 64 rr; forward: L y = -g ; backward: L^T d = y
+        // (active rows: g = 0, L row = e_r)
+        double y[RPL];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int r = lane + 64 * rr;
+          y[rr] = act[r] ? 0.0 : -g[r];
+        }
         for (int c = 0; c < KMAX; ++c) {
           const double yc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
 #pragma unroll
@@ -718,24 +777,24 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
             else if (r < c) y[rr] -= (double)H[c * HLD + r] * dc;
           }
         }
-      }
-      // weights at 0 cannot decrease; a released weight swamped by the coupling
-      // takes its own Newton coordinate step instead
-      const int rel = released >= 0 ? released : 0;
-      double yr = 0.0;
+        // weights at 0 cannot decrease; a released weight swamped by the coupling
+        // takes its own Newton coordinate step instead
+        const int rel = released >= 0 ? released : 0;
+        double yr = 0.0;
 #pragma unroll
-      for (int rr = 0; rr < RPL; ++rr) {
-        const int r = lane + 64 * rr;
-        if (w[r] <= 0.0 && y[rr] < 0.0) y[rr] = 0.0;
-        const double v = __shfl(y[rr], rel & 63, 64);
-        if ((rel >> 6) == rr) yr = v;
-      }
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int r = lane + 64 * rr;
+          if (w[r] <= 0.0 && y[rr] < 0.0) y[rr] = 0.0;
+          const double v = __shfl(y[rr], rel & 63, 64);
+          if ((rel >> 6) == rr) yr = v;
+        }
 #pragma unroll
-      for (int rr = 0; rr < RPL; ++rr) {
-        const int r = lane + 64 * rr;
-        double yv = y[rr];
-        if (released >= 0 && yr <= 0.0) yv = (r == released) ? -g[r] / hdiag_released : 0.0;
-        d[r] = act[r] ? 0.0 : yv;
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int r = lane + 64 * rr;
+          double yv = y[rr];
+          if (released >= 0 && yr <= 0.0) yv = (r == released) ? -g[r] / hdiag_released : 0.0;
+          d[r] = act[r] ? 0.0 : yv;
+        }
       }
     }
     __syncthreads();
