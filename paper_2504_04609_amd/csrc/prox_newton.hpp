@@ -309,6 +309,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   __shared__ int act[KMAX];
   __shared__ int perm[KMAX];  // 64-wide: the free weights in increasing order (compact positions)
   __shared__ int cmp_s[2];    // [0] number of free weights m, [1] compact position of a released weight
+  __shared__ double rt_s[2];  // 64-wide: slope g.d and ratio-test step of this iteration
   __shared__ int ctl[4];
   __shared__ double wHs[KMAX];             // weights of the factor held in H
   __shared__ unsigned long long hmask_s[RPL];  // its active set
@@ -351,35 +352,54 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     if (!have_f) f = pn_eval<MAXB>(p, DTp, ld_dt, n, k, w, s, a, l, tiny, red);  // block_sum synchronises
     have_f = true;
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
+    // Wave v takes columns 16 v .. 16 v + 15 (and 64 more for a 128-wide
+    // dictionary), lane l the bins l, l + 64, ...: coalesced rows of D^T, and
+    // each l_i read once; the 16 column sums then leave the 64 lanes by a
+    // halving butterfly (17 shuffles), lane l ending with column l / 4.
     {
-      // thread (j = lane + 64 cc, q = wave) sums bins i = q, q + 4, ... of column j;
-      // eight independent partial sums keep the D loads in flight
-      const int q = wave;
+      const __amdgpu_buffer_rsrc_t rs = pn_rsrc(DTp, (long long)k * ld_dt);
 #pragma unroll
-      for (int cc = 0; cc < RPL; ++cc) {
-        const int j = lane + 64 * cc;
-        double part[8];
+      for (int cb0 = 0; cb0 < KMAX; cb0 += 64) {
+        const int cb = __builtin_amdgcn_readfirstlane(cb0 + 16 * wave);
+        if (cb < k) {
+          double acc[16];  // columns cb + jj (those past k read row k - 1 and are dropped)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) part[u] = 0.0;
-        if (j < k) {
-          const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
-          const int vj = j * 4;
-          int i = __builtin_amdgcn_readfirstlane(q);
-          for (; i + 60 < n; i += 64) {  // sixteen loads in flight
-            float dv[16];
+          for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+          for (int i0 = 0; i0 < n; i0 += 128) {  // two bin blocks: 32 loads in flight
+            double li[2];
+            float dv[2][16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) dv[u] = pn_ld(rd, vj, (i + 4 * u) * ld_d * 4);
+            for (int sb = 0; sb < 2; ++sb) {
+              const int i = i0 + 64 * sb + lane;
+              const double lv = (double)l[min(i, n - 1)];  // unconditional (clamped) read, then masked
+              li[sb] = i < n ? lv : 0.0;
+              const int vo = min(i, n - 1) * 4;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) part[u & 7] += (double)dv[u] * (double)l[i + 4 * u];
+              for (int jj = 0; jj < 16; ++jj) dv[sb][jj] = pn_ld(rs, vo, min(cb + jj, k - 1) * ld_dt * 4);
+            }
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+              for (int jj = 0; jj < 16; ++jj) acc[jj] += (double)dv[sb][jj] * li[sb];
           }
-          for (; i < n; i += 4) part[0] += (double)pn_ld(rd, vj, i * ld_d * 4) * (double)l[i];
+#pragma unroll
+          for (int o = 32, v = 16; o >= 4; o >>= 1, v >>= 1) {
+            const bool up = (lane & o) != 0;  // keeps the upper half of the values
+#pragma unroll
+            for (int h = 0; h < v / 2; ++h) {
+              const double send = up ? acc[h] : acc[h + v / 2];
+              const double keep = up ? acc[h + v / 2] : acc[h];
+              acc[h] = keep + __shfl_xor(send, o, 64);
+            }
+          }
+          acc[0] += __shfl_xor(acc[0], 2, 64);
+          acc[0] += __shfl_xor(acc[0], 1, 64);
+          const int j = cb + (lane >> 2);
+          if ((lane & 3) == 0 && j < KMAX)
+            g[j] = j < k ? pn_pen_grad(p.pen, w[j], p.alpha, p.beta) + p.eps * acc[0] : 0.0;
+        } else if (cb < KMAX && lane < 16) {
+          g[cb + lane] = 0.0;  // padding columns
         }
-        gp[q * KMAX + j] = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
-      }
-      __syncthreads();
-      if (tid < KMAX) {
-        const double gj = (gp[tid] + gp[KMAX + tid]) + (gp[2 * KMAX + tid] + gp[3 * KMAX + tid]);
-        g[tid] = tid < k ? pn_pen_grad(p.pen, w[tid], p.alpha, p.beta) + p.eps * gj : 0.0;
       }
       __syncthreads();
     }
@@ -750,6 +770,18 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         if (released >= 0 && yr <= 0.0) yv = (x < m && jx == released) ? -g[jx] / hdiag_released : 0.0;
         if (act[lane]) d[lane] = 0.0;
         if (x < m) d[jx] = yv;
+        // ratio test inputs: slope g.d and the step to the first free weight reaching 0
+        double sl = x < m ? g[jx] * yv : 0.0;
+        double tm = (x < m && yv < 0.0) ? -w[jx] / yv : INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          sl += __shfl_xor(sl, off, 64);
+          tm = fmin(tm, __shfl_xor(tm, off, 64));
+        }
+        if (lane == 0) {
+          rt_s[0] = sl;
+          rt_s[1] = tm;
+        }
       } else {
         // lane owns rows lane + 64 rr; forward: L y = -g ; backward: L^T d = y
         // (active rows: g = 0, L row = e_r)
@@ -801,7 +833,10 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
 
     // ---- ratio test and Armijo backtracking
     double slope = 0.0, tmax = INFINITY;
-    {
+    if constexpr (KMAX == 64) {  // reduced by wave 0 with the solve
+      slope = rt_s[0];
+      tmax = rt_s[1];
+    } else {
       const double sl = (tid < KMAX && !act[tid]) ? g[tid] * d[tid] : 0.0;
       const double tm = (tid < KMAX && !act[tid] && d[tid] < 0.0) ? -w[tid] / d[tid] : INFINITY;
       slope = pn_block_sum(sl, red);
