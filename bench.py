@@ -58,6 +58,11 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6, "bf16_mfma": 2500.0}  # TFLOP/s, MI355X
 HEADLINE = "bf16warm_fp32_64"
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# calibrated on a plain copy; valid only for the kernel source it was taken on
+PMC_TRAFFIC = os.path.join(ROOT, "profiles", "pmc_traffic_prox_newton_fp32_warm_n1024_k64_B4096.txt")
+PMC_SOURCE = os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "prox_newton.hpp")
+COPY_BYTES = 256 << 20
 BASELINE_ARM = "fp32_64_cold"
 PROBE = 0.5
 
@@ -96,6 +101,35 @@ def arm_params(name, wl, otlm):
     raise ValueError(name)
 
 
+def pmc_traffic(kernel):
+    """Bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none or the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(PMC_TRAFFIC) as f:
+            kv = dict(ln.split(":", 1) for ln in f if ":" in ln and not ln.startswith("#"))
+        with open(PMC_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    kv = {a.strip(): b.strip() for a, b in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != digest:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_calibration(torch):
+    """One elementwise copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES),
+    three times: the reference dispatch for the FETCH_SIZE / WRITE_SIZE scale."""
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "dispatches": 3}),
+          flush=True)
+
+
 def roofline(prof, B, n, k, phi):
     """Roofline entry for the kernel class with the largest total time."""
     totals = {c: v[0] * v[1] for c, v in prof.items() if isinstance(v, tuple)}
@@ -110,16 +144,19 @@ def roofline(prof, B, n, k, phi):
     elif dom in ("weight_step", "weight_prox_f64") and prof["newton_iters"] > 0:
         # Newton on the weight prox (FP64 arithmetic): every Newton iteration and
         # spectrum takes ~6 n k flop (a = D w and the objective, the gradient, one
-        # line-search evaluation); an iteration that factors anew adds the Hessian's
-        # lower-triangle blocks, 2 n (10/16) 64^2, and the Cholesky factorisation,
-        # 64^3 / 3; the counts are those of this kernel (FP32- or FP64-state) over
+        # line-search evaluation); an iteration that factors anew adds its free-set
+        # Hessian, 2 n flop per lower-triangle entry (m (m + 1) / 2 entries for m
+        # free weights; the Cholesky factorisation, m^3 / 3 < 3 % of that, is not
+        # counted); the counts are those of this kernel (FP32- or FP64-state) over
         # its timed launches.
         sfx = "fp32" if dom == "weight_step" else "fp64"
         nit, nfac = prof["newton_iters_" + sfx], prof["factorisations_" + sfx]
-        flops = (nit * 6.0 * n * k + nfac * (2.0 * n * 64 * 64 * 10 / 16 + 64.0 ** 3 / 3)) / max(cnt, 1)
-        entry.update(newton_iters=nit, factorisations=nfac)
+        nent = prof["hessian_entries_" + sfx]
+        flops = (nit * 6.0 * n * k + nent * 2.0 * n) / max(cnt, 1)
+        entry.update(newton_iters=nit, factorisations=nfac, hessian_entries=nent)
         entry["kernel"] = "prox_newton_kernel<float, float>" if dom == "weight_step" else \
             "prox_newton_kernel<double, double>"
+        entry["traffic"] = pmc_traffic(entry["kernel"])
         entry.update(bound="alu", unit="TFLOP/s", peak=PEAK["fp64_vector"], flops_per_launch=flops)
     else:
         flops = 2.0 * B * n * k
@@ -301,7 +338,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sample", type=int, default=8)
+    ap.add_argument("--sample", type=int, default=512,
+                    help="held-out spectra checked against the oracle (also the CPU-baseline sample)")
     ap.add_argument("--train", type=int, default=200_000, help="training triples for the network")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--save-net", default=None, help="write the trained network to this .npz")
@@ -312,6 +350,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch row")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload row")
     ap.add_argument("--ragged-only", action="store_true", help="run only the ragged-batch row")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (scale for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here (the spectra are "
@@ -322,6 +362,9 @@ def main():
     from paper_2504_04609_amd import otlm, synth, warmstart
     log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
 
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     if args.ragged_only:
         print(json.dumps({"ragged": ragged_row(args, otlm, synth, torch)}), flush=True)
         return

@@ -219,11 +219,12 @@ int otlm_objective(otlm_kernel k, const double* C, const float* D, int64_t kdim,
  *   [11] MM warm-up steps of an exact-prox solve (cold starts, fallbacks)
  * otlm_profile_read copies the mean duration in ms per launch (ms[12]) and the
  * launch counts (count[12]) accumulated since the last enable, synchronising
- * the recorded events first, and the Newton iterations the weight-prox
- * kernels performed, summed over spectra (newton_iters[4]: Newton iterations
- * of the FP32-state and FP64-state kernels, then their Hessian
- * factorisations; a profiled solve synchronises its stream at the end to
- * collect them).  Any output pointer
+ * the recorded events first, and the work the weight-prox kernels performed,
+ * summed over spectra (newton_iters[6]: Newton iterations of the FP32-state
+ * and FP64-state kernels, then their Hessian factorisations, then the
+ * lower-triangle entries m (m + 1) / 2 of the free-set Hessians they built,
+ * m the number of free weights; a profiled solve synchronises its stream at
+ * the end to collect them).  Any output pointer
  * may be NULL.  Enabling resets the counters.  Errors: OTLM_E_INVALID for a
  * null kernel. */
 int otlm_profile_enable(otlm_kernel k, int32_t on);

@@ -58,6 +58,8 @@ struct Workspace {
   int* nit64 = nullptr;  // the same, FP64-state prox
   int* nfac = nullptr;   // Hessian factorisations per spectrum, FP32-state prox
   int* nfac64 = nullptr; // the same, FP64-state prox
+  int* nent = nullptr;   // free-set Hessian entries built per spectrum, FP32-state prox
+  int* nent64 = nullptr; // the same, FP64-state prox
   // stored Cholesky factors of the weight prox (factor reuse), allocated on demand
   int64_t fac_B = 0;
   double *Lg = nullptr, *wH = nullptr;
@@ -91,7 +93,7 @@ struct Workspace {
     ew_prev = nullptr;
     ew_best = nullptr;
     stall = nullptr;
-    nit = nit64 = nfac = nfac64 = nullptr;
+    nit = nit64 = nfac = nfac64 = nent = nent64 = nullptr;
     fac_B = 0;
     Lg = wH = nullptr;
     maskH = nullptr;
@@ -161,7 +163,8 @@ struct otlm_kernel_s {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double prof_ms[OTLM_PROF_CLASSES] = {};
   int64_t prof_n[OTLM_PROF_CLASSES] = {};
-  int64_t prof_newton[4] = {0, 0, 0, 0};  // weight prox: Newton iterations FP32 / FP64 state, then factorisations
+  int64_t prof_newton[6] = {0, 0, 0, 0, 0, 0};  // weight prox: Newton iterations FP32 / FP64 state, then
+                                                 // factorisations, then free-set Hessian entries built
 };
 
 namespace {
@@ -207,6 +210,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.nit64, (size_t)B);
   rc |= dev_alloc(ws, &ws.nfac, (size_t)B);
   rc |= dev_alloc(ws, &ws.nfac64, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nent, (size_t)B);
+  rc |= dev_alloc(ws, &ws.nent64, (size_t)B);
   rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
   rc |= dev_alloc(ws, &ws.xflags, (size_t)B);
   rc |= dev_alloc(ws, &ws.it_base, (size_t)B);
@@ -416,7 +421,7 @@ int otlm_profile_enable(otlm_kernel k, int32_t on) {
     k->prof_ms[c] = 0.0;
     k->prof_n[c] = 0;
   }
-  for (int q = 0; q < 4; ++q) k->prof_newton[q] = 0;
+  for (int q = 0; q < 6; ++q) k->prof_newton[q] = 0;
   k->profile = on != 0;
   return OTLM_OK;
 }
@@ -425,7 +430,7 @@ int otlm_profile_read(otlm_kernel k, double* ms, int64_t* count, int64_t* newton
   if (!k) return OTLM_E_INVALID;
   prof_collect(k);
   if (newton_iters)
-    for (int q = 0; q < 4; ++q) newton_iters[q] = k->prof_newton[q];
+    for (int q = 0; q < 6; ++q) newton_iters[q] = k->prof_newton[q];
   for (int c = 0; c < OTLM_PROF_CLASSES; ++c) {
     if (ms) ms[c] = k->prof_n[c] ? k->prof_ms[c] / (double)k->prof_n[c] : 0.0;
     if (count) count[c] = k->prof_n[c];
@@ -514,6 +519,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     OTLM_HIP(hipMemsetAsync(ws.nit64, 0, (size_t)B * sizeof(int), s));
     OTLM_HIP(hipMemsetAsync(ws.nfac, 0, (size_t)B * sizeof(int), s));
     OTLM_HIP(hipMemsetAsync(ws.nfac64, 0, (size_t)B * sizeof(int), s));
+    OTLM_HIP(hipMemsetAsync(ws.nent, 0, (size_t)B * sizeof(int), s));
+    OTLM_HIP(hipMemsetAsync(ws.nent64, 0, (size_t)B * sizeof(int), s));
     if (OTLM_HESS_REUSE > 0.0 && ws.fac_B < B) {  // factor storage: 32 KB per spectrum; without it, no reuse
       for (void* q : {(void*)ws.Lg, (void*)ws.wH, (void*)ws.maskH, (void*)ws.validH})
         if (q) (void)hipFree(q);
@@ -573,7 +580,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<float, float> a;
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = ws.mm_until; a.it = 0;
-    a.nfac = ws.nfac; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac; a.nent = ws.nent; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
@@ -586,7 +593,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<double, double> a;
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = nullptr; a.it = 0;
-    a.nfac = ws.nfac64; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac64; a.nent = ws.nent64; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
@@ -780,16 +787,20 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   OTLM_HIP(hipGetLastError());
   if (k->profile && exact) {  // Newton iteration count for the roofline of the prox kernel
     std::vector<int> h((size_t)B);
-    std::vector<int> h64((size_t)B), f32((size_t)B), f64((size_t)B);
+    std::vector<int> h64((size_t)B), f32((size_t)B), f64((size_t)B), e32((size_t)B), e64((size_t)B);
     OTLM_HIP(hipMemcpyAsync(h.data(), ws.nit, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipMemcpyAsync(h64.data(), ws.nit64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipMemcpyAsync(f32.data(), ws.nfac, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipMemcpyAsync(f64.data(), ws.nfac64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipMemcpyAsync(e32.data(), ws.nent, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
+    OTLM_HIP(hipMemcpyAsync(e64.data(), ws.nent64, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, s));
     OTLM_HIP(hipStreamSynchronize(s));
     for (int v : h) k->prof_newton[0] += v;
     for (int v : h64) k->prof_newton[1] += v;
     for (int v : f32) k->prof_newton[2] += v;
     for (int v : f64) k->prof_newton[3] += v;
+    for (int v : e32) k->prof_newton[4] += v;
+    for (int v : e64) k->prof_newton[5] += v;
   }
   return OTLM_OK;
 }

@@ -72,6 +72,7 @@ struct ProxNewtonArgs {
   int it;
   int* nit;
   int* nfac;                   // Hessian factorisations, accumulated per spectrum
+  int* nent;                   // free-set Hessian entries m (m + 1) / 2 built, accumulated per spectrum (null: none)
   void* Lg;                    // last Cholesky factor per spectrum, lg_stride bytes each (null: no reuse)
   size_t lg_stride;
   double* wH;                  // [B][128] weights at that factorisation
@@ -319,6 +320,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   double kkt_prev = 0.0;                  // (wave 0) the free gradient of the previous iteration
   int last_reused = 0;                    // (wave 0) the previous step used a reused factor
   int nfac = 0;
+  int nent = 0;  // (thread 0) lower-triangle entries of the free-set Hessians built
 
   for (int i = tid; i < n; i += PN_THREADS) s[i] = srow[i];
   for (int j = tid; j < KMAX; j += PN_THREADS) {
@@ -718,6 +720,15 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         hstate[1] = 1;
       }
       ++nfac;
+      if (tid == 0) {
+        int m = 0;
+        if constexpr (KMAX == 64) {
+          m = cmp_s[0];
+        } else {
+          for (int j = 0; j < k; ++j) m += !act[j];
+        }
+        nent += m * (m + 1) / 2;
+      }
       __syncthreads();
     }
     const double hdiag_released = released >= 0 ? hrel_diag_s : 1.0;
@@ -910,6 +921,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   if (tid == 0) {
     p.nit[b] += it;
     if (p.nfac) p.nfac[b] += nfac;
+    if (p.nent) p.nent[b] += nent;
   }
   if (reuse_on && hstate[1]) {
     for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) Lb[e] = H[(e / KMAX) * HLD + (e % KMAX)];

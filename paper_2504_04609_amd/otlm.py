@@ -208,12 +208,13 @@ class GibbsKernel:
         """Mean ms per launch and launch count for each timed kernel class."""
         ms = (ctypes.c_double * len(PROFILE_CLASSES))()
         cnt = (ctypes.c_int64 * len(PROFILE_CLASSES))()
-        nit = (ctypes.c_int64 * 4)()
+        nit = (ctypes.c_int64 * 6)()
         _check(load().otlm_profile_read(self.handle, ms, cnt, nit), "otlm_profile_read")
         out = {name: (ms[i], cnt[i]) for i, name in enumerate(PROFILE_CLASSES)}
         out["newton_iters"] = nit[0] + nit[1]
         out["newton_iters_fp32"], out["newton_iters_fp64"] = nit[0], nit[1]
         out["factorisations_fp32"], out["factorisations_fp64"] = nit[2], nit[3]
+        out["hessian_entries_fp32"], out["hessian_entries_fp64"] = nit[4], nit[5]
         return out
 
     def close(self):
