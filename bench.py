@@ -293,9 +293,15 @@ def ragged_row(args, otlm, synth, torch):
              "ms_per_launch": ws_ms, "launches": ws_n, "traffic": None,
              "bytes_per_launch": prof["weight_step_bytes"] / max(ws_n, 1)}
     wstep["achieved"] = wstep["bytes_per_launch"] / (ws_ms * 1e-3) / 1e9
-    for e in (prod, wstep):
+    nt_ms, nt_n = prof["weight_prox_newton"]
+    newton = {"kernel": "prox_newton_kernel<float, float, float> (64- and 128-wide launches)", "bound": "alu",
+              "unit": "TFLOP/s", "peak": PEAK["fp64_vector"], "ms_per_launch": nt_ms, "launches": nt_n,
+              "traffic": None, "flops_per_launch": prof["newton_flops"] / max(nt_n, 1)}
+    newton["achieved"] = newton["flops_per_launch"] / (max(nt_ms, 1e-9) * 1e-3) / 1e12
+    entries = (prod, wstep, newton)
+    for e in entries:
         e["frac"] = e["achieved"] / e["peak"]
-    dominant = prod if prod_ms * (kv_n + kt_n) >= ws_ms * ws_n else wstep
+    dominant = max(entries, key=lambda e: e["ms_per_launch"] * e["launches"])
     row = {"workload": wl.name, "B": wl.B, "n": list(ns), "k": sorted(set(int(x) for x in kdim)),
            "datafit": "l2+tv", "lambda": wl.lam, "lambda2": wl.lam2, "penalty": "l2sq", "alpha": wl.alpha,
            "eps": wl.eps, "dtype": "f32", "inner_mm_steps": 4, "tile": info["tile"], "tile_tune_ms": info["tune_ms"],
@@ -305,7 +311,7 @@ def ragged_row(args, otlm, synth, torch):
            "status_counts": {int(a): int(b) for a, b in zip(*np.unique(status, return_counts=True))},
            "kernels_ms_per_launch": {c: v[0] for c, v in prof.items() if isinstance(v, tuple)},
            "kernel_launches": {c: v[1] for c, v in prof.items() if isinstance(v, tuple)},
-           "roofline": dominant, "roofline_other": wstep if dominant is prod else prod}
+           "roofline": dominant, "roofline_other": [e for e in entries if e is not dominant]}
     if not args.no_cpu:
         import oracle as orc
         n_of = np.array(ns)[kernel_of]

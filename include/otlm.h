@@ -264,7 +264,7 @@ typedef struct {
                           grouped kernel products (128x128, 128x64, 64x128,
                           64x64) on the plan's own shapes at create and keep
                           the fastest; 0..3: use that shape                  */
-  int32_t newton_after;/* 60 (default): a spectrum with kdim <= 128 and
+  int32_t newton_after;/* 15 (default): a spectrum with kdim <= 128 and
                           n <= 2048 still active after this many iterations
                           takes the exact weight prox (active-set Newton, as
                           OTLM_WSTEP_EXACT; FP64 Hessian for kdim <= 64, FP32
@@ -272,7 +272,7 @@ typedef struct {
   int32_t reserved;    /* set to 0                                            */
 } otlm_ragged_opts;
 
-/* use_graph = 1, tile = -1, newton_after = 60. */
+/* use_graph = 1, tile = -1, newton_after = 15. */
 void otlm_ragged_default_opts(otlm_ragged_opts* o);
 
 /* Plan a ragged solve.
@@ -315,10 +315,13 @@ int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* 
  * t = K^T u products with the target prox  [3] convergence test
  * [4] Newton weight prox.  While
  * enabled the solve launches eagerly (no graph replay) and counts the
- * algorithmic work of the timed launches into work[2] (may be NULL):
+ * algorithmic work of the timed launches into work[3] (may be NULL):
  * [0] multiply-adds of the kernel products, sum over launches and active
  * spectra of n_b^2 (both products); [1] bytes of the weight steps, per active
- * spectrum 4 (4 n_b + band entries of D_b + 2 kdim[b]).  Reading synchronises
+ * spectrum 4 (4 n_b + band entries of D_b + 2 kdim[b]); [2] flops of the
+ * Newton weight prox, per Newton iteration 6 n_b kdim[b] (evaluation,
+ * gradient, one trial point) plus 2 n_b per lower-triangle entry of the
+ * free-set Hessians built.  Reading synchronises
  * the device. */
 int otlm_ragged_profile_enable(otlm_ragged r, int32_t on);
 int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count, int64_t* work);

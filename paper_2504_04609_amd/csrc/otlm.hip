@@ -580,7 +580,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<float, float> a;
     a.S = ws.S; a.W = ws.W; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = ws.mm_until; a.it = 0;
-    a.nfac = ws.nfac; a.nent = ws.nent; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac; a.nent = ws.nent; a.flops = nullptr; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
@@ -593,7 +593,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     ProxNewtonArgs<double, double> a;
     a.S = ws.S64; a.W = ws.W64; a.Dp = ws.Dp; a.DTp = ws.DTp; a.ld_dt = (int)np; a.colc = ws.colc; a.done = ws.done;
     a.mm_until = nullptr; a.it = 0;
-    a.nfac = ws.nfac64; a.nent = ws.nent64; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
+    a.nfac = ws.nfac64; a.nent = ws.nent64; a.flops = nullptr; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
     a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;

@@ -73,6 +73,8 @@ struct ProxNewtonArgs {
   int* nit;
   int* nfac;                   // Hessian factorisations, accumulated per spectrum
   int* nent;                   // free-set Hessian entries m (m + 1) / 2 built, accumulated per spectrum (null: none)
+  unsigned long long* flops;   // algorithmic flops of all spectra, accumulated (null: none): per Newton iteration
+                               // 6 n k, per free-set Hessian entry built 2 n
   void* Lg;                    // last Cholesky factor per spectrum, lg_stride bytes each (null: no reuse)
   size_t lg_stride;
   double* wH;                  // [B][128] weights at that factorisation
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   __shared__ int act[KMAX];
   __shared__ int perm[KMAX];  // 64-wide: the free weights in increasing order (compact positions)
   __shared__ int cmp_s[2];    // [0] number of free weights m, [1] compact position of a released weight
-  __shared__ double rt_s[2];  // 64-wide: slope g.d and ratio-test step of this iteration
+  __shared__ double rt_s[2];  // slope g.d and ratio-test step of this iteration
   __shared__ int ctl[4];
   __shared__ double wHs[KMAX];             // weights of the factor held in H
   __shared__ unsigned long long hmask_s[RPL];  // its active set
@@ -327,6 +329,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     const double wj = j < k ? (double)wrow[j] : 0.0;
     w[j] = wj > 0.0 ? wj : 0.0;
     act[j] = (j < k && wj > 0.0) ? 0 : 1;   // padded columns stay active at 0
+    g[j] = 0.0;                             // (the gradient sweep writes j < k only)
   }
   const bool reuse_on = p.Lg && p.reuse_tol > 0.0;
   TH* Lb = reuse_on ? reinterpret_cast<TH*>(reinterpret_cast<char*>(p.Lg) + (size_t)b * p.lg_stride) : nullptr;
@@ -354,25 +357,31 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     if (!have_f) f = pn_eval<MAXB>(p, DTp, ld_dt, n, k, w, s, a, l, tiny, red);  // block_sum synchronises
     have_f = true;
     // ---- gradient: g_j = alpha R'(w_j) + eps sum_i D_ij log(a_i / s_i)
-    // Wave v takes columns 16 v .. 16 v + 15 (and 64 more for a 128-wide
-    // dictionary), lane l the bins l, l + 64, ...: coalesced rows of D^T, and
-    // each l_i read once; the 16 column sums then leave the 64 lanes by a
-    // halving butterfly (17 shuffles), lane l ending with column l / 4.
+    // Column groups of 16 (G = ceil(k/16), at most 4 per pass; a 128-wide
+    // dictionary takes two passes), lanes over bins: coalesced rows of D^T and
+    // each l_i read once; with G <= 2 the P = 4/G waves of a group split the
+    // 64-bin blocks and their partial sums meet in LDS.  The 16 column sums of
+    // a wave leave the 64 lanes by a halving butterfly (17 shuffles), lane l
+    // ending with column l / 4.
     {
       const __amdgpu_buffer_rsrc_t rs = pn_rsrc(DTp, (long long)k * ld_dt);
+      const int G = min((k + 15) >> 4, 4);
+      const int P = G == 1 ? 4 : (G == 2 ? 2 : 1);
+      const int wv = __builtin_amdgcn_readfirstlane(wave);
+      const int cg = wv % G, bp = wv / G;
 #pragma unroll
       for (int cb0 = 0; cb0 < KMAX; cb0 += 64) {
-        const int cb = __builtin_amdgcn_readfirstlane(cb0 + 16 * wave);
-        if (cb < k) {
+        const int cb = cb0 + 16 * cg;
+        if (bp < P && cb < k) {
           double acc[16];  // columns cb + jj (those past k read row k - 1 and are dropped)
 #pragma unroll
           for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-          for (int i0 = 0; i0 < n; i0 += 128) {  // two bin blocks: 32 loads in flight
+          for (int blk = 2 * bp; 64 * blk < n; blk += 2 * P) {  // two 64-bin blocks: 32 loads in flight
             double li[2];
             float dv[2][16];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
-              const int i = i0 + 64 * sb + lane;
+              const int i = 64 * (blk + sb) + lane;
               const double lv = (double)l[min(i, n - 1)];  // unconditional (clamped) read, then masked
               li[sb] = i < n ? lv : 0.0;
               const int vo = min(i, n - 1) * 4;
@@ -397,10 +406,18 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           acc[0] += __shfl_xor(acc[0], 2, 64);
           acc[0] += __shfl_xor(acc[0], 1, 64);
           const int j = cb + (lane >> 2);
-          if ((lane & 3) == 0 && j < KMAX)
-            g[j] = j < k ? pn_pen_grad(p.pen, w[j], p.alpha, p.beta) + p.eps * acc[0] : 0.0;
-        } else if (cb < KMAX && lane < 16) {
-          g[cb + lane] = 0.0;  // padding columns
+          if ((lane & 3) == 0 && j < KMAX) {
+            if (P == 1) g[j] = j < k ? pn_pen_grad(p.pen, w[j], p.alpha, p.beta) + p.eps * acc[0] : 0.0;
+            else gp[bp * KMAX + j] = acc[0];
+          }
+        }
+      }
+      if (P > 1) {  // k <= 32: sum the bin parts in part order
+        __syncthreads();
+        if (tid < KMAX) {
+          double gj = 0.0;
+          for (int q = 0; q < P; ++q) gj += gp[q * KMAX + tid];
+          g[tid] = tid < k ? pn_pen_grad(p.pen, w[tid], p.alpha, p.beta) + p.eps * gj : 0.0;
         }
       }
       __syncthreads();
@@ -593,32 +610,66 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           default: hessian(std::integral_constant<int, 4>{}); break;
         }
       } else {
-        // 256 register blocks of 8 x 8 entries (block row bj, block column bl = 0..15)
-        const int bj = tid >> 4, bl = tid & 15;
-        TH acc[8][8];
+        // FP32 matrix cores (v_mfma_f32_32x32x2_f32): the 10 lower 32 x 32 blocks
+        // (p >= q) of the 4 x 4 block grid, 2 or 3 per wave over all bins, so no
+        // cross-wave sum: wave 0 (0,0) (1,0) (1,1); 1 (2,0) (2,1) (2,2); 2 (3,0)
+        // (3,1); 3 (3,2) (3,3).  In a step lane l supplies bin 2 st + l/32 and
+        // column 32 p + l%32 of panel p, as the A operand (scaled by 1 / a_i)
+        // and as the B operand; lane l, register r of a block hold its row
+        // 8 (r/4) + 4 (l/32) + r%4, column l%32.
+        const int l32 = lane & 31, kh = lane >> 5;
+        const int nst = (n + 1) >> 1;
+        const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
+        auto run = [&](auto w_c) {
+          constexpr int W = decltype(w_c)::value;
+          constexpr int NB = W < 2 ? 3 : 2;
+          constexpr int BP[4][3] = {{0, 1, 1}, {2, 2, 2}, {3, 3, 0}, {3, 3, 0}};
+          constexpr int BQ[4][3] = {{0, 0, 1}, {0, 1, 2}, {0, 1, 0}, {2, 3, 0}};
+          typedef float f32x16 __attribute__((ext_vector_type(16)));
+          f32x16 acc[NB];
 #pragma unroll
-        for (int x = 0; x < 8; ++x)
+          for (int x = 0; x < NB; ++x)
 #pragma unroll
-          for (int y = 0; y < 8; ++y) acc[x][y] = (TH)0;
-        const float* rowj = Dp + bj * 8;
-        const float* rowl = Dp + bl * 8;
-        for (int i = 0; i < n; ++i) {
-          const float4 ja = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d);
-          const float4 jb = *reinterpret_cast<const float4*>(rowj + (size_t)i * ld_d + 4);
-          const float4 la = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d);
-          const float4 lb = *reinterpret_cast<const float4*>(rowl + (size_t)i * ld_d + 4);
-          const TH sc = (TH)ra[i];  // 1 / a_i
-          const TH xa[8] = {ja.x * sc, ja.y * sc, ja.z * sc, ja.w * sc, jb.x * sc, jb.y * sc, jb.z * sc, jb.w * sc};
-          const TH xb[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+            for (int r = 0; r < 16; ++r) acc[x][r] = 0.f;
+          auto load_step = [&](int st, float (&v)[4], float& sc) {
+            const int i = 2 * st + kh;
+            const bool in = i < n;
+            const int ro = (min(i, n - 1) * ld_d + l32) * 4;
 #pragma unroll
-          for (int x = 0; x < 8; ++x)
+            for (int pp = 0; pp < 4; ++pp) {
+              bool need = false;
 #pragma unroll
-            for (int y = 0; y < 8; ++y) acc[x][y] += xa[x] * xb[y];
+              for (int x = 0; x < NB; ++x) need = need || BP[W][x] == pp || BQ[W][x] == pp;
+              v[pp] = (need && in) ? pn_ld(rd, ro, 128 * pp) : 0.f;
+            }
+            sc = in ? (float)ra[min(i, n - 1)] : 0.f;
+          };
+          auto mfma_step = [&](const float (&v)[4], float sc) {
+#pragma unroll
+            for (int x = 0; x < NB; ++x)
+              acc[x] = __builtin_amdgcn_mfma_f32_32x32x2f32(v[BP[W][x]] * sc, v[BQ[W][x]], acc[x], 0, 0, 0);
+          };
+          float v0[4], v1[4], s0, s1;
+          load_step(0, v0, s0);
+          load_step(1, v1, s1);
+          for (int st = 0; st < nst; st += 2) {
+            mfma_step(v0, s0);
+            load_step(st + 2, v0, s0);
+            mfma_step(v1, s1);
+            load_step(st + 3, v1, s1);
+          }
+#pragma unroll
+          for (int x = 0; x < NB; ++x)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              H[(32 * BP[W][x] + 8 * (r >> 2) + 4 * kh + (r & 3)) * HLD + 32 * BQ[W][x] + l32] = (TH)acc[x][r];
+        };
+        switch (__builtin_amdgcn_readfirstlane(wave)) {
+          case 0: run(std::integral_constant<int, 0>{}); break;
+          case 1: run(std::integral_constant<int, 1>{}); break;
+          case 2: run(std::integral_constant<int, 2>{}); break;
+          default: run(std::integral_constant<int, 3>{}); break;
         }
-#pragma unroll
-        for (int x = 0; x < 8; ++x)
-#pragma unroll
-          for (int y = 0; y < 8; ++y) H[(bj * 8 + x) * HLD + bl * 8 + y] = acc[x][y];
         __syncthreads();
       }
       if constexpr (KMAX == 64) {
@@ -795,29 +846,51 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
         }
       } else {
         // lane owns rows lane + 64 rr; forward: L y = -g ; backward: L^T d = y
-        // (active rows: g = 0, L row = e_r)
-        double y[RPL];
+        // (active rows: g = 0, L row = e_r); y_c and 1 / L_cc broadcast by
+        // v_readlane
+        double y[RPL], inv[RPL];
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
           const int r = lane + 64 * rr;
           y[rr] = act[r] ? 0.0 : -g[r];
+          inv[rr] = 1.0 / (double)H[r * HLD + r];
         }
-        for (int c = 0; c < KMAX; ++c) {
-          const double yc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+        for (int cb = 0; cb < KMAX; cb += 8) {  // L rows 8 entries at a time, read ahead of the chain
+          TH lr[RPL][8];
 #pragma unroll
-          for (int rr = 0; rr < RPL; ++rr) {
-            const int r = lane + 64 * rr;
-            if (r == c) y[rr] = yc;
-            else if (r > c) y[rr] -= (double)H[r * HLD + c] * yc;
+          for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int r = lane + 64 * rr;
+              const TH v = H[r * HLD + cb + u];
+              lr[rr][u] = cb + u < r ? v : (TH)0;
+            }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int c = cb + u;
+            const double yc = pn_readlane(c < 64 ? y[0] : y[RPL - 1], c & 63) *
+                              pn_readlane(c < 64 ? inv[0] : inv[RPL - 1], c & 63);
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) y[rr] = lane + 64 * rr == c ? yc : y[rr] - (double)lr[rr][u] * yc;
           }
         }
-        for (int c = KMAX - 1; c >= 0; --c) {
-          const double dc = __shfl(y[c >> 6], c & 63, 64) / (double)H[c * HLD + c];
+        for (int cb = KMAX - 8; cb >= 0; cb -= 8) {
+          TH lc[RPL][8];
 #pragma unroll
-          for (int rr = 0; rr < RPL; ++rr) {
-            const int r = lane + 64 * rr;
-            if (r == c) y[rr] = dc;
-            else if (r < c) y[rr] -= (double)H[c * HLD + r] * dc;
+          for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int r = lane + 64 * rr;
+              const TH v = H[(cb + u) * HLD + r];
+              lc[rr][u] = cb + u > r ? v : (TH)0;
+            }
+#pragma unroll
+          for (int u = 7; u >= 0; --u) {
+            const int c = cb + u;
+            const double dc = pn_readlane(c < 64 ? y[0] : y[RPL - 1], c & 63) *
+                              pn_readlane(c < 64 ? inv[0] : inv[RPL - 1], c & 63);
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) y[rr] = lane + 64 * rr == c ? dc : y[rr] - (double)lc[rr][u] * dc;
           }
         }
         // weights at 0 cannot decrease; a released weight swamped by the coupling
@@ -831,28 +904,34 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           const double v = __shfl(y[rr], rel & 63, 64);
           if ((rel >> 6) == rr) yr = v;
         }
+        double sl = 0.0, tm = INFINITY;
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
           const int r = lane + 64 * rr;
           double yv = y[rr];
           if (released >= 0 && yr <= 0.0) yv = (r == released) ? -g[r] / hdiag_released : 0.0;
-          d[r] = act[r] ? 0.0 : yv;
+          yv = act[r] ? 0.0 : yv;
+          d[r] = yv;
+          if (!act[r]) {  // ratio test inputs, as in the 64-wide path
+            sl += g[r] * yv;
+            if (yv < 0.0) tm = fmin(tm, -w[r] / yv);
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          sl += __shfl_xor(sl, off, 64);
+          tm = fmin(tm, __shfl_xor(tm, off, 64));
+        }
+        if (lane == 0) {
+          rt_s[0] = sl;
+          rt_s[1] = tm;
         }
       }
     }
     __syncthreads();
 
     // ---- ratio test and Armijo backtracking
-    double slope = 0.0, tmax = INFINITY;
-    if constexpr (KMAX == 64) {  // reduced by wave 0 with the solve
-      slope = rt_s[0];
-      tmax = rt_s[1];
-    } else {
-      const double sl = (tid < KMAX && !act[tid]) ? g[tid] * d[tid] : 0.0;
-      const double tm = (tid < KMAX && !act[tid] && d[tid] < 0.0) ? -w[tid] / d[tid] : INFINITY;
-      slope = pn_block_sum(sl, red);
-      tmax = pn_block_min(tm, red);
-    }
+    const double slope = rt_s[0], tmax = rt_s[1];  // reduced by wave 0 with the solve
     bool accepted = false, evaluated = false;
     double t = fmin(1.0, tmax), fn = 0.0;
     // trial point w + t d clipped at 0; at t = tmax the weights that stop the
@@ -922,6 +1001,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     p.nit[b] += it;
     if (p.nfac) p.nfac[b] += nfac;
     if (p.nent) p.nent[b] += nent;
+    if (p.flops) atomicAdd(p.flops, 6ull * (unsigned long long)it * n * k + 2ull * (unsigned long long)nent * n);
   }
   if (reuse_on && hstate[1]) {
     for (int e = tid; e < KMAX * KMAX; e += PN_THREADS) Lb[e] = H[(e / KMAX) * HLD + (e % KMAX)];

@@ -54,7 +54,7 @@ struct otlm_ragged_s {
   double *Lg = nullptr, *wH = nullptr;
   unsigned long long* maskH = nullptr;
   int *validH = nullptr, *nit = nullptr, *nfac = nullptr;
-  unsigned long long* work = nullptr;  // profiling: [0] kernel-product MACs, [1] weight-step bytes
+  unsigned long long* work = nullptr;  // profiling: [0] kernel-product MACs, [1] weight-step bytes, [2] Newton flops
   int* act_rows = nullptr;
   RgGroups gi{};
   float4* colc = nullptr;
@@ -331,7 +331,7 @@ void otlm_ragged_default_opts(otlm_ragged_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->use_graph = 1;
   o->tile = -1;
-  o->newton_after = 60;
+  o->newton_after = 15;
 }
 
 int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32_t* kernel_of, const int32_t* kdim,
@@ -473,7 +473,7 @@ int otlm_ragged_create(const otlm_kernel* kernels, int32_t nkernels, const int32
             r->alloc(&r->pwn, B) && r->alloc(&r->pwd, B) && r->alloc(&r->ew_prev, B) && r->alloc(&r->ew_best, B) &&
             r->alloc(&r->done, B) && r->alloc(&r->iters, B) && r->alloc(&r->status, B) && r->alloc(&r->flags, 4) &&
             r->alloc(&r->stall, B) && r->alloc(&r->it_dev, 1) && r->alloc(&r->act, 1) &&
-            r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 2) &&
+            r->alloc(&r->act_rows, B) && r->alloc(&r->nband, B) && r->alloc(&r->work, 3) &&
             r->alloc(&r->Dp, r->tot_dp) && r->alloc(&r->pnspec, B) && r->alloc(&r->nit, B) &&
             r->alloc(&r->nfac, B) && r->alloc(&r->validH, B) && r->alloc(&r->maskH, 2 * B) &&
             r->alloc(&r->wH, r->n_newton ? B * 128 : 1) &&
@@ -565,7 +565,7 @@ int otlm_ragged_info(otlm_ragged r, int32_t* tile_bm, int32_t* tile_bn, double* 
 int otlm_ragged_profile_enable(otlm_ragged r, int32_t on) {
   if (!r) return OTLM_E_INVALID;
   rg_prof_collect(r);
-  OTLM_HIP(hipMemset(r->work, 0, 2 * sizeof(unsigned long long)));
+  OTLM_HIP(hipMemset(r->work, 0, 3 * sizeof(unsigned long long)));
   for (int c = 0; c < RG_PROF_CLASSES; ++c) {
     r->prof_ms[c] = 0.0;
     r->prof_n[c] = 0;
@@ -578,11 +578,12 @@ int otlm_ragged_profile_read(otlm_ragged r, double* ms, int64_t* count, int64_t*
   if (!r) return OTLM_E_INVALID;
   rg_prof_collect(r);
   if (work) {
-    unsigned long long h[2] = {0, 0};
+    unsigned long long h[3] = {0, 0, 0};
     OTLM_HIP(hipDeviceSynchronize());
     OTLM_HIP(hipMemcpy(h, r->work, sizeof(h), hipMemcpyDeviceToHost));
     work[0] = (int64_t)h[0];
     work[1] = (int64_t)h[1];
+    work[2] = (int64_t)h[2];
   }
   for (int c = 0; c < RG_PROF_CLASSES; ++c) {
     if (ms) ms[c] = r->prof_n[c] ? r->prof_ms[c] / (double)r->prof_n[c] : 0.0;

@@ -278,7 +278,7 @@ class RaggedPlan:
     kdim[b] columns.  Packed layouts as in include/otlm.h."""
 
     def __init__(self, kernels, kernel_of, kdim, params: SolveParams, use_graph: bool = True, tile: int = -1,
-                 newton_after: int = 60, stream=None):
+                 newton_after: int = 15, stream=None):
         import numpy as np
         self.kernels = list(kernels)  # the plan reads their K: keep them alive
         self.kernel_of = np.ascontiguousarray(kernel_of, dtype=np.int32)
@@ -321,10 +321,10 @@ class RaggedPlan:
     def profile_read(self):
         ms = (ctypes.c_double * len(RAGGED_PROFILE_CLASSES))()
         cnt = (ctypes.c_int64 * len(RAGGED_PROFILE_CLASSES))()
-        work = (ctypes.c_int64 * 2)()
+        work = (ctypes.c_int64 * 3)()
         _check(load().otlm_ragged_profile_read(self.handle, ms, cnt, work), "otlm_ragged_profile_read")
         out = {name: (ms[i], cnt[i]) for i, name in enumerate(RAGGED_PROFILE_CLASSES)}
-        out["product_macs"], out["weight_step_bytes"] = work[0], work[1]
+        out["product_macs"], out["weight_step_bytes"], out["newton_flops"] = work[0], work[1], work[2]
         return out
 
     def solve(self, D, Y, W=None, logV=None, want_logU=True, stream=None):

@@ -144,9 +144,9 @@ def test_input_order_does_not_change_a_spectrum(small):
 def test_inner_steps_keep_the_fixed_point(small):
     """One and eight MM steps per iteration converge to the same weights (the
     repetitions change the path, not the limit); more steps need fewer
-    iterations."""
-    _, one = small.solve(params(SMALL, inner_max=1))
-    _, eight = small.solve(params(SMALL, inner_max=8))
+    iterations.  MM steps only (no Newton prox after some iterations)."""
+    _, one = small.solve(params(SMALL, inner_max=1), newton_after=-1)
+    _, eight = small.solve(params(SMALL, inner_max=8), newton_after=-1)
     for b in range(0, SMALL.B, 3):
         ref = small.oracle(b)["W"][0]
         assert rel_err(small.w(one, b), ref) <= 1e-5
@@ -155,9 +155,10 @@ def test_inner_steps_keep_the_fixed_point(small):
 
 
 def test_single_mm_step_path_matches_oracle(small):
-    """Fixed iteration count (tol 0): with one MM step per iteration the GPU
-    follows the oracle's single-step path, not only its limit."""
-    _, res = small.solve(params(SMALL, inner_max=1, tol=0.0, max_iter=25))
+    """Fixed iteration count (tol 0): with one MM step per iteration (and no
+    Newton prox) the GPU follows the oracle's single-step path, not only its
+    limit."""
+    _, res = small.solve(params(SMALL, inner_max=1, tol=0.0, max_iter=25), newton_after=-1)
     assert (res["iters"] == 25).all() and (res["status"] == otlm.STATUS_MAX_ITER).all()
     for b in (1, 7, 19):
         ref = small.oracle(b, mode="single", max_iter=25, tol=0.0)

@@ -68,7 +68,7 @@ def test_ragged_opts_and_argument_errors():
     assert ctypes.sizeof(otlm.RaggedOpts) == 16
     o = otlm.RaggedOpts()
     lib.otlm_ragged_default_opts(ctypes.byref(o))
-    assert o.use_graph == 1 and o.tile == -1 and o.newton_after == 60
+    assert o.use_graph == 1 and o.tile == -1 and o.newton_after == 15
     p = otlm.Params()
     lib.otlm_default_params(ctypes.byref(p))
     h = ctypes.c_void_p()
