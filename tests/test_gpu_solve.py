@@ -261,6 +261,26 @@ def test_exact_prox_ridge_agrees_with_mm_fixed_point():
     assert rel_err(a["W"], b["W"]).max() <= 1e-5
 
 
+@pytest.mark.parametrize("k,pen,alpha", [(5, "l1", 1e-2), (16, "l1", 1e-2), (17, "l1", 1e-2), (33, "l1", 1e-2),
+                                         (48, "l1", 1e-2), (63, "l1", 1e-2), (40, "l2sq", 1e-3), (63, "l2sq", 1e-3)])
+def test_exact_prox_every_dictionary_width(k, pen, alpha):
+    """Exact weight prox with FP64 refinement for dictionary widths on both sides
+    of the kernel's 16-column boundaries: the gradient splits bins over the idle
+    waves (k <= 32), leaves one wave idle (33..48) or uses all four (> 48); the l1
+    free sets (5..27 weights) take 1 or 2 compact Hessian panels, the ridge ones
+    (every weight free) 3 or 4.  n = 200 leaves a ragged tail in every bin sweep.
+    Bar: 1e-5 on every spectrum."""
+    wl = synth.Workload(f"width{k}", n=200, k=k, B=6, eps=0.01, fit="kl", pen=pen, lam=1.0, alpha=alpha, seed=21)
+    D32, Y32, C = setup(wl, range(wl.B))
+    ref = oracle_solve(C, D32, Y32, wl, max_iter=600, tol=1e-11, mode="exact")
+    assert ref["converged"].all()
+    _, res = gpu_solve(C, D32, Y32, wl, tol=1e-9, bulk_tol=1e-4, max_iter=400, check_every=5, wstep="exact",
+                       inner_max=8, refine="fp64", refine_sweeps=300)
+    assert np.all(res["status"] == otlm.STATUS_CONVERGED), res["status"]
+    err = rel_err(res["W"], ref["W"])
+    assert err.max() <= 1e-5, err
+
+
 def test_exact_prox_rejects_large_dictionaries():
     n, k = 128, 80
     dic = synth.make_dictionary(n, k, 4)
