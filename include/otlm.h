@@ -135,12 +135,16 @@ typedef struct {
                             kdim <= 64 and n <= 1024; the first 3 iterations of
                             a cold start take the MM step)                          */
   int32_t inner_max;     /* Newton iterations per weight prox (WSTEP_EXACT), >= 1  */
+  int32_t refine_check_every; /* convergence test cadence of the refinement phase,
+                            >= 0 (0: check_every); the refinement phase is short
+                            and its stopping rule needs two test intervals, so a
+                            short cadence ends it sooner; default 2              */
 } otlm_params;
 
 /* Fill `p` with defaults: KL datafit, no penalty, eps = lambda = 1, tol 1e-6,
  * bulk_tol 1e-4, absorb_tau 30, no warm probe, max_iter 1000, check_every 10, FP32, no refinement
- * (refine_sweeps 200 when enabled), cold start, one MM step per iteration,
- * inner_max 5. */
+ * (refine_sweeps 200 and refine_check_every 2 when enabled), cold start, one MM
+ * step per iteration, inner_max 5. */
 void otlm_default_params(otlm_params* p);
 
 /* Build the Gibbs kernel K = exp(-C / eps) (Algorithm 1, initialisation).

@@ -300,6 +300,7 @@ bool params_valid(const otlm_params* p, double kernel_eps) {
   if (p->prec != OTLM_PREC_FP32 && p->prec != OTLM_PREC_BF16) return false;
   if (p->refine < OTLM_REFINE_NONE || p->refine > OTLM_REFINE_FP64) return false;
   if (p->refine != OTLM_REFINE_NONE && p->refine_sweeps < 1) return false;
+  if (p->refine_check_every < 0) return false;
   if (!(p->bulk_tol >= 0.0) || !(p->warm_probe >= 0.0) || !(p->absorb_tau >= 0.0)) return false;
   return true;
 }
@@ -325,6 +326,7 @@ void otlm_default_params(otlm_params* p) {
   p->absorb_tau = 30.0;
   p->wstep = OTLM_WSTEP_MM;
   p->inner_max = 5;
+  p->refine_check_every = 2;
 }
 
 const char* otlm_status_str(int code) {
@@ -700,13 +702,13 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   const bool absorb = fp64 && p->absorb_tau > 0.0;
   // probe: test the warm start at the first convergence test of this phase
   auto run_phase = [&](int it0, int cap, double tol, float floor_w, bool use64, bool bf16, int nts_phase,
-                       bool probe) -> int {
+                       bool probe, int cadence) -> int {
     int it = it0;
     if (tol > 0.0) weight_change(use64, 1);
     bool first_check = true;
     for (int j = 1; j <= cap; ++j) {
       it = it0 + j;
-      const bool chk = (tol > 0.0) && (j % p->check_every == 0 || j == cap);
+      const bool chk = (tol > 0.0) && (j % cadence == 0 || j == cap);
       if (use64) iterate64(it, chk);
       else iterate32(it, chk, bf16);
       if (chk) {
@@ -754,7 +756,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
   const bool probe = p->warm && p->warm_probe > 0.0;
   int last = run_phase(0, p->max_iter, refine ? p->bulk_tol : p->tol, bulk_bf16 ? OTLM_BF16_FLOOR : OTLM_FP32_FLOOR,
-                       false, bulk_bf16, nts, probe);
+                       false, bulk_bf16, nts, probe, p->check_every);
+  const int refine_cadence = p->refine_check_every > 0 ? p->refine_check_every : p->check_every;
   if (last < 0) return last;
   bool state64 = false;
   if (refine) {
@@ -770,11 +773,11 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       OTLM_HIP(hipGetLastError());
       const int nts64 = (int)((np + G64_BN - 1) / G64_BN);
       last = run_phase(std::max(last, mm_until_max), p->refine_sweeps, p->tol, OTLM_FP64_FLOOR, true, false, nts64,
-                       false);
+                       false, refine_cadence);
       state64 = true;
     } else {
       last = run_phase(std::max(last, mm_until_max), p->refine_sweeps, p->tol, OTLM_FP32_FLOOR, false, false, nts,
-                       false);
+                       false, refine_cadence);
     }
     if (last < 0) return last;
   }

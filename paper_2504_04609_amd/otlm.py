@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("fit", ctypes.c_int32),
                 ("pen", ctypes.c_int32), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32), ("wstep", ctypes.c_int32),
-                ("inner_max", ctypes.c_int32)]
+                ("inner_max", ctypes.c_int32), ("refine_check_every", ctypes.c_int32)]
 
 
 class AdamW(ctypes.Structure):
@@ -148,6 +148,7 @@ class SolveParams:
     absorb_tau: float = 30.0    # FP64 refinement: move spectra with |log u| or |log v| above it to FP64
     wstep: str = "mm"           # "mm" (one MM step, Algorithm 1) or "exact" (ProxP by Newton)
     inner_max: int = 5
+    refine_check_every: int = 2  # convergence test cadence of the refinement phase (0: check_every)
 
     def c(self) -> Params:
         p = Params()
@@ -161,6 +162,7 @@ class SolveParams:
         p.warm_probe = self.warm_probe
         p.absorb_tau = self.absorb_tau
         p.wstep, p.inner_max = WSTEP[self.wstep], self.inner_max
+        p.refine_check_every = self.refine_check_every
         return p
 
 

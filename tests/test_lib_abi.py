@@ -37,11 +37,11 @@ def test_library_exports_every_declared_symbol():
 @needs_lib
 def test_params_struct_matches_header():
     # 9 doubles + 10 int32 in include/otlm.h
-    assert ctypes.sizeof(otlm.Params) == 9 * 8 + 10 * 4
+    assert ctypes.sizeof(otlm.Params) == 9 * 8 + 11 * 4 + 4  # eleven int32 fields, tail padding to 8 bytes
     p = otlm.Params()
     otlm.load().otlm_default_params(ctypes.byref(p))
     assert p.fit == otlm.FIT["kl"] and p.pen == otlm.PEN["none"] and p.max_iter == 1000
-    assert p.check_every == 10 and p.tol == pytest.approx(1e-6)
+    assert p.check_every == 10 and p.tol == pytest.approx(1e-6) and p.refine_check_every == 2
     assert p.wstep == 0 and p.inner_max == 5 and p.refine == 0 and p.refine_sweeps == 200
     assert p.bulk_tol == pytest.approx(1e-4) and p.absorb_tau == 30.0 and p.warm_probe == 0.0
 
