@@ -225,9 +225,11 @@ __device__ __forceinline__ void gemm_nt_f32_tile(const GemmArgs& g, const Epi& e
   }
 }
 
+// rowidx (may be null): rows 0 .. g.M - 1 of the product are rows rowidx[m]
+// of A and of the epilogue (the active spectra of a batch).
 template <int BM, int BN, class Epi>
-__global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi) {
-  gemm_nt_f32_tile<BM, BN, Epi>(g, epi, blockIdx.y * BM, blockIdx.x * BN, blockIdx.x);
+__global__ __launch_bounds__(256) void gemm_nt_f32(GemmArgs g, Epi epi, const int* __restrict__ rowidx) {
+  gemm_nt_f32_tile<BM, BN, Epi>(g, epi, blockIdx.y * BM, blockIdx.x * BN, blockIdx.x, rowidx);
 }
 
 // Any of the four operand layouts (see gemm_nt_f32_tile).

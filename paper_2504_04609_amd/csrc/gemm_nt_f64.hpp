@@ -32,8 +32,10 @@ __device__ __forceinline__ double red_op64(double a, double b) {
   return IS_MAX ? fmax(a, b) : a + b;
 }
 
+// rowidx (may be null): rows 0 .. g.M - 1 of the product are rows rowidx[m]
+// of A and of the epilogue (the active spectra of a batch).
 template <class Epi>
-__global__ __launch_bounds__(256) void gemm_nt_f64(GemmArgs64 g, Epi epi) {
+__global__ __launch_bounds__(256) void gemm_nt_f64(GemmArgs64 g, Epi epi, const int* __restrict__ rowidx) {
   constexpr int BM = G64_BM, BN = G64_BN, BK = G64_BK, LD = G64_LD;
   __shared__ __attribute__((aligned(16))) double As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) double Bs[2][BN * LD];
@@ -45,12 +47,18 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(GemmArgs64 g, Epi epi) {
 
   // global loads: a 64 x 16 tile = 512 pairs of doubles, 2 per thread per operand
   f64x2 ra[2], rb[2];
+  const double* arow[2];  // A row of each staged pair (null: beyond M)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int idx = tid + q * 256, r = idx >> 3, gm = m0 + r;
+    arow[q] = gm < g.M ? g.A + (size_t)(rowidx ? rowidx[gm] : gm) * g.lda : nullptr;
+  }
   auto gload = [&](int kt) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + q * 256, r = idx >> 3, c = (idx & 7) * 2;
-      const int gm = m0 + r, gn = n0 + r;
-      ra[q] = gm < g.M ? *reinterpret_cast<const f64x2*>(g.A + (size_t)gm * g.lda + kt * BK + c) : f64x2{0.0, 0.0};
+      const int gn = n0 + r;
+      ra[q] = arow[q] ? *reinterpret_cast<const f64x2*>(arow[q] + kt * BK + c) : f64x2{0.0, 0.0};
       rb[q] = gn < g.N ? *reinterpret_cast<const f64x2*>(g.Bt + (size_t)gn * g.ldb + kt * BK + c) : f64x2{0.0, 0.0};
     }
   };
@@ -107,10 +115,11 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(GemmArgs64 g, Epi epi) {
       const int m = m0 + row;
       double red[2] = {0.0, 0.0};
       if (m < g.M) {
+        const int mr = rowidx ? rowidx[m] : m;
 #pragma unroll
         for (int fn = 0; fn < 2; ++fn) {
           const int n = n0 + wn * 32 + fn * 16 + l16;
-          if (n < g.N) epi.elem(m, n, acc[fm][fn][r], red);
+          if (n < g.N) epi.elem(mr, n, acc[fm][fn][r], red);
         }
       }
       if constexpr (Epi::NRED > 0) {
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void gemm_nt_f64(GemmArgs64 g, Epi epi) {
           double v[2];
           v[0] = red_op64<Epi::RED_IS_MAX[0]>(red_s[0][row][0], red_s[1][row][0]);
           v[1] = red_op64<Epi::RED_IS_MAX[1]>(red_s[0][row][1], red_s[1][row][1]);
-          epi.row_partial(m, blockIdx.x, v);
+          epi.row_partial(rowidx ? rowidx[m] : m, blockIdx.x, v);
         }
       }
     }

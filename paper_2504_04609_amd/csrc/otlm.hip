@@ -68,6 +68,7 @@ struct Workspace {
   int* mm_until = nullptr;  // last iteration of each spectrum's MM warm-up (exact weight prox)
   int* xflags = nullptr;    // status bits set on the way: 16 warm start replaced, 32 range promotion
   int* it_base = nullptr;   // per-spectrum offset of refinement-phase iteration indices
+  int* act_rows = nullptr;  // active spectra after the last convergence test (compacted products)
   unsigned short *Vbf = nullptr, *Ubf = nullptr;
   // FP64 refinement state
   int64_t B64 = 0;
@@ -98,7 +99,7 @@ struct Workspace {
     Lg = wH = nullptr;
     maskH = nullptr;
     validH = nullptr;
-    mm_until = xflags = it_base = nullptr;
+    mm_until = xflags = it_base = act_rows = nullptr;
     Vbf = Ubf = nullptr;
   }
   void release64() {
@@ -215,6 +216,7 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.mm_until, (size_t)B);
   rc |= dev_alloc(ws, &ws.xflags, (size_t)B);
   rc |= dev_alloc(ws, &ws.it_base, (size_t)B);
+  rc |= dev_alloc(ws, &ws.act_rows, (size_t)B);
   rc |= dev_alloc(ws, &ws.Vbf, bn);
   rc |= dev_alloc(ws, &ws.Ubf, bn);
   if (rc != OTLM_OK) {
@@ -232,11 +234,13 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
 }
 
 // Tile shapes of the four products (chosen per problem size).
+// rowidx (may be null): the g.M product rows are rows rowidx[0 .. g.M) of A
+// and of the epilogue.
 template <class Epi>
-void gemm(int bm, int bn, const GemmArgs& g, const Epi& e, hipStream_t s) {
+void gemm(int bm, int bn, const GemmArgs& g, const Epi& e, hipStream_t s, const int* rowidx = nullptr) {
   auto launch = [&](auto kern, int BM, int BN) {
     dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
-    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g, e);
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g, e, rowidx);
   };
   if (bm == 128 && bn == 128) launch(gemm_nt_f32<128, 128, Epi>, 128, 128);
   else if (bm == 128 && bn == 64) launch(gemm_nt_f32<128, 64, Epi>, 128, 64);
@@ -607,6 +611,14 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   // Last iteration at which some spectrum still takes the MM step in the exact
   // mode (cold starts: OTLM_MM_WARMUP; warm starts: none; a fallback restarts it).
   int mm_until_max = (exact && !p->warm) ? OTLM_MM_WARMUP : 0;
+  // Rows of the FP32 / FP64 kernel products: all spectra at the start of a
+  // phase, then the active ones listed after each convergence test (spectra
+  // that stopped are frozen, so their rows need no products).  A full product
+  // fills the chip with one wave of 128-row tiles, so once the active rows
+  // fall to half the batch the products take 64-row tiles (and K^T u 64 x 64)
+  // to keep the tile count up.
+  int Ma = M;
+  const int* arows = nullptr;
   // One FP32 iteration (bulk phase or FP32 refinement); `it` counts from 1 over the whole solve.
   auto iterate32 = [&](int it, bool chk, bool bf16) {
     const bool mm_step = !exact || it <= mm_until_max;
@@ -619,8 +631,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
         hipLaunchKernelGGL(gemm_nt_bf16<EpiSrc>, grid, dim3(256), 0, s, g, e);
       } else {
         ProfScope ps(k, PROF_KV32, s);
-        GemmArgs g{ws.V, (int)np, k->K, (int)np, M, (int)np, (int)np};
-        gemm(bm_k, bn_k, g, e, s);
+        GemmArgs g{ws.V, (int)np, k->K, (int)np, Ma, (int)np, (int)np};
+        gemm(2 * Ma <= M ? 64 : bm_k, bn_k, g, e, s, arows);
       }
     }
     if (exact) {  // weight prox solved by active-set Newton (spectra past their MM warm-up)
@@ -632,15 +644,15 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
     if (mm_step) {  // MM weight step (every spectrum, or those in their warm-up)
       ProfScope ps(k, exact ? PROF_WMM32 : PROF_W32, s);
-      GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, M, (int)kp, (int)np};
+      GemmArgs g{ws.R, (int)np, ws.DTp, (int)np, Ma, (int)kp, (int)np};
       EpiWupd e{ws.W, ws.colc, ws.done, exact ? ws.mm_until : nullptr, it, (int)kp, (int)kdim, p->pen, false};
-      gemm(64, bn_w, g, e, s);
+      gemm(64, bn_w, g, e, s, arows);
     }
     {  // a = D w, u = a / s
       ProfScope ps(k, PROF_U32, s);
-      GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
+      GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, Ma, (int)np, (int)kp};
       EpiUscale e{ws.A, ws.U, ws.S, (int)np, (int)n, false, bf16 ? ws.Ubf : nullptr};
-      gemm(64, 128, g, e, s);
+      gemm(64, 128, g, e, s, arows);
     }
     {  // t = K^T u, v = prox(t | y) / t
       EpiProx e{ws.V, Y, ws.done, pc, (int)np, (int)n, (int)n, false, bf16 ? ws.Vbf : nullptr};
@@ -651,20 +663,21 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
         hipLaunchKernelGGL(gemm_nt_bf16<EpiProx>, grid, dim3(256), 0, s, g, e);
       } else {
         ProfScope ps(k, PROF_KTU32, s);
-        GemmArgs g{ws.U, (int)np, k->KT, (int)np, M, (int)np, (int)np};
-        gemm(bm_k, bn_k, g, e, s);
+        GemmArgs g{ws.U, (int)np, k->KT, (int)np, Ma, (int)np, (int)np};
+        if (2 * Ma <= M) gemm(64, 64, g, e, s, arows);
+        else gemm(bm_k, bn_k, g, e, s, arows);
       }
     }
   };
   // One FP64 iteration (refinement phase, exact weight prox).
   auto iterate64 = [&](int, bool chk) {
     const int ntiles64 = (int)((np + G64_BN - 1) / G64_BN);
-    dim3 grid_n((unsigned)((np + G64_BN - 1) / G64_BN), (unsigned)((B + G64_BM - 1) / G64_BM));
+    dim3 grid_n((unsigned)((np + G64_BN - 1) / G64_BN), (unsigned)((Ma + G64_BM - 1) / G64_BM));
     {
       ProfScope ps(k, PROF_KV64, s);
-      GemmArgs64 g{ws.V64, (int)np, k->K64p, (int)np, M, (int)np, (int)np};
+      GemmArgs64 g{ws.V64, (int)np, k->K64p, (int)np, Ma, (int)np, (int)np};
       EpiSrc64 e{ws.S64, ws.A64, ws.U64, ws.psn, ws.psd, (int)np, (int)n, ntiles64, chk};
-      hipLaunchKernelGGL(gemm_nt_f64<EpiSrc64>, grid_n, dim3(256), 0, s, g, e);
+      hipLaunchKernelGGL(gemm_nt_f64<EpiSrc64>, grid_n, dim3(256), 0, s, g, e, arows);
     }
     {
       ProfScope ps(k, PROF_W64, s);
@@ -674,15 +687,15 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     }
     {
       ProfScope ps(k, PROF_U64, s);
-      GemmArgs64 g{ws.W64, (int)kp, ws.Dp64, (int)kp, M, (int)np, (int)kp};
+      GemmArgs64 g{ws.W64, (int)kp, ws.Dp64, (int)kp, Ma, (int)np, (int)kp};
       EpiUscale64 e{ws.A64, ws.U64, ws.S64, (int)np, (int)n, false};
-      hipLaunchKernelGGL(gemm_nt_f64<EpiUscale64>, grid_n, dim3(256), 0, s, g, e);
+      hipLaunchKernelGGL(gemm_nt_f64<EpiUscale64>, grid_n, dim3(256), 0, s, g, e, arows);
     }
     {
       ProfScope ps(k, PROF_KTU64, s);
-      GemmArgs64 g{ws.U64, (int)np, k->KT64p, (int)np, M, (int)np, (int)np};
+      GemmArgs64 g{ws.U64, (int)np, k->KT64p, (int)np, Ma, (int)np, (int)np};
       EpiProx64 e{ws.V64, Y, ws.done, pc64, (int)np, (int)n, (int)n, false};
-      hipLaunchKernelGGL(gemm_nt_f64<EpiProx64>, grid_n, dim3(256), 0, s, g, e);
+      hipLaunchKernelGGL(gemm_nt_f64<EpiProx64>, grid_n, dim3(256), 0, s, g, e, arows);
     }
   };
   // Runs one phase; returns the last iteration index or a negative status.
@@ -706,6 +719,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     int it = it0;
     if (tol > 0.0) weight_change(use64, 1);
     bool first_check = true;
+    Ma = M;  // every spectrum of the phase is active until its first test
+    arows = nullptr;
     for (int j = 1; j <= cap; ++j) {
       it = it0 + j;
       const bool chk = (tol > 0.0) && (j % cadence == 0 || j == cap);
@@ -731,10 +746,14 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
           hipLaunchKernelGGL(range_check, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, (const float*)ws.U,
                              (const float*)ws.V, (int)n, (int)np, M, (float)p->absorb_tau, it, ws.done, ws.status,
                              ws.iters, ws.xflags, ws.flags);
+        // the active list, and its count in flags[0], after every change of done
+        hipLaunchKernelGGL(compact_active, dim3(1), dim3(1024), 0, s, (const int*)ws.done, M, ws.act_rows, ws.flags);
         if (hipGetLastError() != hipSuccess) return OTLM_E_HIP;
         if (hipMemcpyAsync(ws.host_flags, ws.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
           return OTLM_E_HIP;
+        Ma = ws.host_flags[0] > 0 ? ws.host_flags[0] : M;
+        arows = Ma < M ? ws.act_rows : nullptr;
         if (fb && ws.host_flags[2] > 0) {  // restarted spectra: a = D w0, and their MM warm-up
           GemmArgs g{ws.W, (int)kp, ws.Dp, (int)kp, M, (int)np, (int)kp};
           EpiStore e{ws.A, (int)np, (int)n, false};

@@ -406,6 +406,34 @@ __global__ __launch_bounds__(256) void range_check(const float* __restrict__ U, 
   }
 }
 
+// Active spectra after a convergence test (and the warm-start fallback and
+// range promotion that follow it): rows[0 .. c) = the b with done[b] == 0 in
+// increasing order, and flags[0] = c, the count the host reads.  One
+// workgroup, wave ballots.
+__global__ __launch_bounds__(1024) void compact_active(const int* __restrict__ done, int B, int* __restrict__ rows,
+                                                        int* __restrict__ flags) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int base = 0;
+  for (int c0 = 0; c0 < B; c0 += 1024) {
+    const int r = c0 + tid;
+    const bool on = r < B && !done[r];
+    const unsigned long long m = __ballot(on);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      off += w < wave ? wsum[w] : 0;
+      tot += wsum[w];
+    }
+    if (on) rows[base + off + before] = r;
+    base += tot;
+    __syncthreads();
+  }
+  if (tid == 0) flags[0] = base;
+}
+
 // Weight change over a check interval, per spectrum: max_j |w_j - w^snap_j|
 // and max_j |w_j|, where w^snap holds the weights at the previous test; then
 // w^snap = w.  With init = 1 it only takes the snapshot (start of a phase).
