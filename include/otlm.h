@@ -110,8 +110,9 @@ typedef struct {
   double bulk_tol;       /* bulk-phase tolerance when a refinement follows, >= 0   */
   double warm_probe;     /* > 0 with warm = 1: at the first convergence test, a
                             spectrum whose weight change over the interval
-                            exceeds warm_probe relative to max|w| (or is not
-                            finite) restarts from the cold start and is flagged
+                            exceeds warm_probe relative to the weights in the l1
+                            norm, sum|w - w_start| / sum|w| (or is not finite),
+                            restarts from the cold start and is flagged
                             OTLM_S_FALLBACK; 0: no probe                          */
   double absorb_tau;     /* with REFINE_FP64: at every convergence test of the
                             bulk phase a spectrum with |log u_i| or |log v_i| >

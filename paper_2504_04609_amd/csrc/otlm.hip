@@ -49,6 +49,7 @@ struct Workspace {
   float *Dp = nullptr, *DTp = nullptr;
   float4* colc = nullptr;
   float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr;
+  float *pln = nullptr, *pld = nullptr;  // l1 weight change and l1 weights of the last interval (warm-start probe)
   float* Wsnap = nullptr;  // weights at the previous convergence test
   int *done = nullptr, *iters = nullptr, *status = nullptr, *flags = nullptr;
   float* ew_prev = nullptr;
@@ -88,7 +89,7 @@ struct Workspace {
     if (host_flags) (void)hipHostFree(host_flags);
     host_flags = nullptr;
     B = np = kp = 0;
-    V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = Wsnap = nullptr;
+    V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = pln = pld = Wsnap = nullptr;
     colc = nullptr;
     done = iters = status = flags = nullptr;
     ew_prev = nullptr;
@@ -199,6 +200,8 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.psd, (size_t)B * MAX_TILES);
   rc |= dev_alloc(ws, &ws.pwn, (size_t)B);
   rc |= dev_alloc(ws, &ws.pwd, (size_t)B);
+  rc |= dev_alloc(ws, &ws.pln, (size_t)B);
+  rc |= dev_alloc(ws, &ws.pld, (size_t)B);
   rc |= dev_alloc(ws, &ws.Wsnap, bk);
   rc |= dev_alloc(ws, &ws.done, (size_t)B);
   rc |= dev_alloc(ws, &ws.iters, (size_t)B);
@@ -705,10 +708,11 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     if (use64) {
       auto kern = interval_change<double>;
       hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W64, (int)kp, (int)kdim, M, ws.Wsnap64, init, ws.pwn,
-                         ws.pwd);
+                         ws.pwd, ws.pln, ws.pld);
     } else {
       auto kern = interval_change<float>;
-      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W, (int)kp, (int)kdim, M, ws.Wsnap, init, ws.pwn, ws.pwd);
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, ws.W, (int)kp, (int)kdim, M, ws.Wsnap, init, ws.pwn, ws.pwd,
+                         ws.pln, ws.pld);
     }
   };
   // range promotion of the FP32 bulk phase (needs the FP64 phase to continue in)
@@ -736,8 +740,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
         }
         const bool fb = probe && first_check;
         if (fb)
-          hipLaunchKernelGGL(warm_fallback, dim3((unsigned)B), dim3(256), 0, s, (const float*)ws.pwn,
-                             (const float*)ws.pwd, (float)p->warm_probe, Y, (const float4*)ws.colc, (int)n,
+          hipLaunchKernelGGL(warm_fallback, dim3((unsigned)B), dim3(256), 0, s, (const float*)ws.pln,
+                             (const float*)ws.pld, (float)p->warm_probe, Y, (const float4*)ws.colc, (int)n,
                              (int)kdim, (int)np, (int)kp, it, exact ? OTLM_MM_WARMUP : 0, ws.V,
                              bf16 ? ws.Vbf : nullptr, ws.W, ws.Wsnap, ws.U, ws.done, ws.status, ws.ew_prev,
                              ws.ew_best, ws.stall, ws.mm_until, ws.xflags, ws.flags + 2);

@@ -330,12 +330,13 @@ __global__ void init_state(const float* __restrict__ Y, const float* __restrict_
 }
 
 // Fallback of a warm start: at the first convergence test, a spectrum whose
-// weight change over the interval exceeds `probe` relative to max|w| (or is
-// not finite) is restarted from the cold start (v = 1, w0_j = sum(y)/(k x_j),
-// u = 0), takes MM steps up to iteration it + mm_warmup, and is flagged (bit
-// 16 of xflags).  The caller recomputes a = D w afterwards.  One workgroup per
-// spectrum.
-__global__ void warm_fallback(const float* __restrict__ pwn, const float* __restrict__ pwd, float probe,
+// weight change over the interval exceeds `probe` relative to the weights in
+// the l1 norm, sum|w - w_start| / sum|w| (pln / pld; a good prediction errs on
+// a few weights, a bad one on all of them), or is not finite, is restarted
+// from the cold start (v = 1, w0_j = sum(y)/(k x_j), u = 0), takes MM steps up
+// to iteration it + mm_warmup, and is flagged (bit 16 of xflags).  The caller
+// recomputes a = D w afterwards.  One workgroup per spectrum.
+__global__ void warm_fallback(const float* __restrict__ pln, const float* __restrict__ pld, float probe,
                               const float* __restrict__ Y, const float4* __restrict__ colc, int n, int k, int np,
                               int kp, int it, int mm_warmup, float* __restrict__ V, unsigned short* __restrict__ Vbf,
                               float* __restrict__ W, float* __restrict__ Wsnap, float* __restrict__ U,
@@ -343,7 +344,7 @@ __global__ void warm_fallback(const float* __restrict__ pwn, const float* __rest
                               float* __restrict__ ew_best, int* __restrict__ stall, int* __restrict__ mm_until,
                               int* __restrict__ xflags, int* __restrict__ count) {
   const int b = blockIdx.x;
-  const float d = pwd[b] > 0.f ? pwn[b] / pwd[b] : 0.f;
+  const float d = pld[b] > 0.f ? pln[b] / pld[b] : 0.f;
   if (d <= probe) return;  // also skips nothing for NaN: NaN fails the comparison and falls back
   __shared__ double ssum[256];
   double acc = 0.0;
@@ -435,33 +436,45 @@ __global__ __launch_bounds__(1024) void compact_active(const int* __restrict__ d
 }
 
 // Weight change over a check interval, per spectrum: max_j |w_j - w^snap_j|
-// and max_j |w_j|, where w^snap holds the weights at the previous test; then
-// w^snap = w.  With init = 1 it only takes the snapshot (start of a phase).
-// NaN propagates into the maxima.  One wave per spectrum.
+// and max_j |w_j|, where w^snap holds the weights at the previous test (the
+// stopping rule), and, when pln is not null, sum_j |w_j - w^snap_j| and
+// sum_j |w_j| (the warm-start probe); then w^snap = w.  With init = 1 it only
+// takes the snapshot (start of a phase).  NaN propagates into the maxima and
+// the sums.  One wave per spectrum.
 __device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
 
 template <class T>
 __global__ __launch_bounds__(256) void interval_change(const T* __restrict__ W, int ld, int k, int B,
                                                        T* __restrict__ snap, int init, float* __restrict__ pwn,
-                                                       float* __restrict__ pwd) {
+                                                       float* __restrict__ pwd, float* __restrict__ pln,
+                                                       float* __restrict__ pld) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (b >= B) return;
-  double dw = 0.0, wm = 0.0;
+  double dw = 0.0, wm = 0.0, ds = 0.0, ws = 0.0;
   for (int j = lane; j < k; j += 64) {
     const size_t o = (size_t)b * ld + j;
     const T w = W[o];
-    dw = nan_max(dw, fabs((double)w - (double)snap[o]));
+    const double dj = fabs((double)w - (double)snap[o]);
+    dw = nan_max(dw, dj);
     wm = nan_max(wm, fabs((double)w));
+    ds += dj;
+    ws += fabs((double)w);
     snap[o] = w;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     dw = nan_max(dw, __shfl_xor(dw, off, 64));
     wm = nan_max(wm, __shfl_xor(wm, off, 64));
+    ds += __shfl_xor(ds, off, 64);
+    ws += __shfl_xor(ws, off, 64);
   }
   if (lane == 0 && !init) {
     pwn[b] = (float)dw;
     pwd[b] = (float)wm;
+    if (pln) {
+      pln[b] = (float)ds;
+      pld[b] = (float)ws;
+    }
   }
 }
 
