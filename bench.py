@@ -59,9 +59,12 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6, "bf16_mfma": 2500.0}  # TFLOP/s, MI355X
 HEADLINE = "bf16warm_fp32_64"
 # HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# calibrated on a plain copy; valid only for the kernel source it was taken on
+# calibrated on a plain copy; valid only for the kernel source, the solver engine
+# and the benchmark settings it was taken with (their sha256 together)
 PMC_TRAFFIC = os.path.join(ROOT, "profiles", "pmc_traffic_prox_newton_fp32_warm_n1024_k64_B4096.txt")
-PMC_SOURCE = os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "prox_newton.hpp")
+PMC_SOURCES = [os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "prox_newton.hpp"),
+               os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "otlm.hip"),
+               os.path.abspath(__file__)]
 COPY_BYTES = 256 << 20
 BASELINE_ARM = "fp32_64_cold"
 # warm-start probe: l1 relative weight change over the first test interval. On the
@@ -109,19 +112,28 @@ def arm_params(name, wl, otlm):
     raise ValueError(name)
 
 
+def sources_digest():
+    """sha256 over the files that decide the measured kernel's launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in PMC_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def pmc_traffic(kernel):
     """Bytes per launch of `kernel` from the committed counter summary, or None
-    when there is none or the kernel source has changed since it was taken."""
-    import hashlib
+    when there is none or the kernel, the engine or the benchmark settings have
+    changed since it was taken."""
     try:
         with open(PMC_TRAFFIC) as f:
             kv = dict(ln.split(":", 1) for ln in f if ":" in ln and not ln.startswith("#"))
-        with open(PMC_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = sources_digest()
     except OSError:
         return None
     kv = {a.strip(): b.strip() for a, b in kv.items()}
-    if kv.get("kernel") != kernel or kv.get("source_sha256") != digest:
+    if kv.get("kernel") != kernel or kv.get("sources_sha256") != digest:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
