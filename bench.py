@@ -31,7 +31,10 @@ Arms (through the C-ABI):
   bf16warm_bf16_64  the same with BF16 bulk kernel products
 
 Secondary rows: "batched" (the batched workload, eps = 0.005, cold FP32 +
-FP64) and "ragged" (skip with --no-ragged): 8192 spectra with their own grid
+FP64), "small_eps" (the same at eps = 0.001: BF16 bulk + 20 FP32 refinement
+sweeps, BF16 bulk + FP64 refinement, FP32 bulk + FP64 refinement, each with its
+weight-error quantiles on 256 oracle-checked spectra; skip with --no-small-eps)
+and "ragged" (skip with --no-ragged): 8192 spectra with their own grid
 length n in {256, 512, 1024, 2048} and dictionary (k in {16..128} Gaussian
 peaks), L2 + TV datafit (1.0, 0.1), ridge 1e-3, eps 0.005, FP32, solved by one
 otlm_ragged plan (grouped kernel products, banded dictionary steps with 4 MM
@@ -272,6 +275,50 @@ def batched_row(args, otlm, synth, torch, orc):
     return row
 
 
+SMALL_EPS_ARMS = ("bf16_32", "bf16_64", "fp32_64")
+
+
+def small_eps_row(args, otlm, synth, torch, orc):
+    """The small-eps workload (the batched one at eps = 0.001), cold: BF16 bulk
+    products then 20 FP32 refinement sweeps, BF16 bulk then FP64 refinement (with
+    range promotion above |log u| = 30), and FP32 bulk then FP64 refinement.  The
+    weight error of each arm against the FP64 oracle on 256 sampled spectra."""
+    wl = synth.CONFIG3
+    dic = wl.dictionary()
+    D = dic.D.astype(np.float32)
+    C = wl.cost()
+    Dt = torch.as_tensor(D, device="cuda:0")
+    Yt = wl.targets_fast(dic=dic, device="cuda:0")
+    kern = otlm.GibbsKernel(torch.as_tensor(C, device="cuda:0"), wl.eps)
+    exact = dict(eps=wl.eps, fit=wl.fit, pen=wl.pen, lam=wl.lam, alpha=wl.alpha, check_every=5, max_iter=400,
+                 wstep="exact", inner_max=8, tol=1e-7)
+    params = {"bf16_32": otlm.SolveParams(**exact, bulk_tol=1e-3, prec="bf16", refine="fp32", refine_sweeps=20),
+              "bf16_64": otlm.SolveParams(**exact, bulk_tol=1e-3, prec="bf16", refine="fp64", refine_sweeps=300),
+              "fp32_64": otlm.SolveParams(**exact, bulk_tol=1e-4, refine="fp64", refine_sweeps=300)}
+    row = {"workload": wl.name, "B": wl.B, "n": wl.n, "k": wl.k, "eps": wl.eps, "arms": {}}
+    W = {}
+    for arm in SMALL_EPS_ARMS:
+        ms, _, out = timed(lambda p=params[arm]: kern.solve(Dt, Yt, p), max(1, min(args.steps, 3)), args.warmup,
+                           torch)
+        st = out["status"].cpu().numpy()
+        W[arm] = out["W"].cpu().numpy()
+        row["arms"][arm] = {"ms_per_solve": ms, "iters_mean": float(out["iters"].float().mean()),
+                            "status_counts": {int(s): int(c) for s, c in zip(*np.unique(st, return_counts=True))},
+                            "absorbed": int(np.sum(st & otlm.STATUS_ABSORBED > 0))}
+    if orc is not None:
+        pick = np.sort(np.random.default_rng(3).choice(wl.B, min(256, wl.B), replace=False))
+        ref, dt = oracle_reference(orc, C, wl, D, Yt.cpu().numpy()[pick])
+        row["oracle_sample"] = {"spectra": len(pick), "seconds": dt}
+        for arm in SMALL_EPS_ARMS:
+            a = row["arms"][arm]
+            err = np.linalg.norm(W[arm][pick].astype(np.float64) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            a["check"] = check(W[arm][pick], ref)
+            a["err_quantiles_50_90_99_max"] = [float(x) for x in np.quantile(err, [0.5, 0.9, 0.99, 1.0])]
+            a["spectra_solved_per_s"] = wl.B * a["check"]["fraction"] / (a["ms_per_solve"] * 1e-3)
+    kern.close()
+    return row
+
+
 def ragged_row(args, otlm, synth, torch):
     """Ragged batch: time per solve, spectra/s, sampled oracle check, roofline."""
     wl = synth.CONFIG4
@@ -375,6 +422,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch row")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload row")
+    ap.add_argument("--no-small-eps", action="store_true", help="skip the small-eps (0.001) row")
     ap.add_argument("--ragged-only", action="store_true", help="run only the ragged-batch row")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scale for the HBM counters)")
@@ -500,6 +548,8 @@ def main():
         line["cpu_baseline"] = cpu
     if not args.no_batched:
         line["batched"] = batched_row(args, otlm, synth, torch, orc)
+    if not args.no_small_eps:
+        line["small_eps"] = small_eps_row(args, otlm, synth, torch, orc)
     if not args.no_ragged:
         line["ragged"] = ragged_row(args, otlm, synth, torch)
     print(json.dumps(line), flush=True)
