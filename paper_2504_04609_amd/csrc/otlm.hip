@@ -48,6 +48,7 @@ struct Workspace {
   float *V = nullptr, *S = nullptr, *R = nullptr, *A = nullptr, *U = nullptr, *W = nullptr;
   float *Dp = nullptr, *DTp = nullptr;
   float4* colc = nullptr;
+  int2* band = nullptr;  // rows of the nonzero entries of each dictionary column
   float *psn = nullptr, *psd = nullptr, *pwn = nullptr, *pwd = nullptr;
   float *pln = nullptr, *pld = nullptr;  // l1 weight change and l1 weights of the last interval (warm-start probe)
   float* Wsnap = nullptr;  // weights at the previous convergence test
@@ -91,6 +92,7 @@ struct Workspace {
     B = np = kp = 0;
     V = S = R = A = U = W = Dp = DTp = psn = psd = pwn = pwd = pln = pld = Wsnap = nullptr;
     colc = nullptr;
+    band = nullptr;
     done = iters = status = flags = nullptr;
     ew_prev = nullptr;
     ew_best = nullptr;
@@ -196,6 +198,7 @@ int ensure_workspace(otlm_kernel k, int64_t B, int64_t kp) {
   rc |= dev_alloc(ws, &ws.Dp, (size_t)np * kp);
   rc |= dev_alloc(ws, &ws.DTp, (size_t)kp * np);
   rc |= dev_alloc(ws, &ws.colc, (size_t)kp);
+  rc |= dev_alloc(ws, &ws.band, (size_t)kp);
   rc |= dev_alloc(ws, &ws.psn, (size_t)B * MAX_TILES);
   rc |= dev_alloc(ws, &ws.psd, (size_t)B * MAX_TILES);
   rc |= dev_alloc(ws, &ws.pwn, (size_t)B);
@@ -551,7 +554,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   }
   OTLM_HIP(hipMemsetAsync(ws.it_base, 0, (size_t)B * sizeof(int), s));
   hipLaunchKernelGGL(prep_dictionary, dim3((unsigned)kp), dim3(256), 0, s, D, (int)n, (int)kdim, (int)np, (int)kp,
-                     p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.flags + 1);
+                     p->pen, p->eps, p->alpha, p->beta, ws.Dp, ws.DTp, ws.colc, ws.band, ws.flags + 1);
   hipLaunchKernelGGL(init_state, dim3((unsigned)B), dim3(256), 0, s, Y, (const float*)W, (const float*)logV,
                      (const float4*)ws.colc, (int)n, (int)kdim, (int)np, (int)kp, p->warm, ws.V, ws.W, ws.U,
                      ws.done, ws.status, ws.iters, ws.ew_prev, ws.ew_best, ws.stall, ws.mm_until,
@@ -591,7 +594,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.mm_until = ws.mm_until; a.it = 0;
     a.nfac = ws.nfac; a.nent = ws.nent; a.flops = nullptr; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
-    a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
+    a.rg = nullptr; a.band = ws.band; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta;
     a.gtol = fp64 ? OTLM_BULK_GTOL : 1e-13;
@@ -604,7 +607,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     a.mm_until = nullptr; a.it = 0;
     a.nfac = ws.nfac64; a.nent = ws.nent64; a.flops = nullptr; a.Lg = reuse ? ws.Lg : nullptr; a.lg_stride = (size_t)PN_K * PN_K * sizeof(double); a.wH = ws.wH; a.maskH = ws.maskH; a.validH = ws.validH;
     a.reuse_tol = OTLM_HESS_REUSE;
-    a.rg = nullptr; a.it_dev = nullptr; a.newton_after = 0;
+    a.rg = nullptr; a.band = ws.band; a.it_dev = nullptr; a.newton_after = 0;
     a.ld_s = (int)np; a.ld_w = (int)kp; a.ld_d = (int)kp; a.n = (int)n; a.k = (int)kdim; a.pen = p->pen;
     a.max_newton = p->inner_max; a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.gtol = 1e-13;
     a.nit = ws.nit64;

@@ -82,6 +82,8 @@ struct ProxNewtonArgs {
   int* validH;                 // [B] 1 when the stored factor may be used
   double reuse_tol;
   const PnSpec* rg;            // ragged layout (null: batch layout)
+  const int2* band;            // per dictionary column its rows with nonzero entries, [lo, hi) (null: unknown;
+                               // batch: [k], ragged: indexed like W); orders the free weights of the 64-wide prox
   const int* it_dev;           // ragged: the iteration counter ...
   int newton_after;            // ... spectra take the prox once it exceeds this
   int ld_s, ld_w, ld_d, ld_dt, n, k, pen, max_newton;
@@ -212,7 +214,7 @@ __device__ __forceinline__ double pn_pen_grad(int pen, double w, double alpha, d
 // factor of the gradient.  Each thread owns up to MAXB bins and keeps their
 // sums independent so the D^T loads overlap.
 template <int MAXB, class TS, class TW, class TL>
-__device__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int ld_dt, int n, int k,
+__device__ __forceinline__ double pn_eval(const ProxNewtonArgs<TS, TW>& p, const float* DTp, int ld_dt, int n, int k,
                           const double* w, const TS* s, TL* a, TL* l, double tiny, double* red) {
   double ai[MAXB];
   int vo[MAXB];  // byte offsets of this thread's bins in a row of D^T, clamped into the row
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   int n = p.n, k = p.k, ld_d = p.ld_d, ld_dt = p.ld_dt, ld_w = p.ld_w;
   const float* Dp = p.Dp;
   const float* DTp = p.DTp;
+  const int2* band = p.band;
   const TS* srow = p.S + (size_t)b * p.ld_s;
   TW* wrow = p.W + (size_t)b * p.ld_w;
   if (p.rg) {  // ragged: this spectrum's own sizes and arrays, once it is past its MM iterations
@@ -291,6 +294,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
     DTp = p.DTp + sp.dt_off;
     srow = p.S + sp.s_off;
     wrow = p.W + sp.w_off;
+    if (band) band += sp.w_off;
   }
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -310,7 +314,10 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   TL* lt = at + n;                                         // [n]
   TS* s = reinterpret_cast<TS*>(lt + n);                   // [n]
   __shared__ int act[KMAX];
-  __shared__ int perm[KMAX];  // 64-wide: the free weights in increasing order (compact positions)
+  __shared__ int perm[KMAX];  // 64-wide: the free weights in column order (compact positions)
+  __shared__ int ord_s[KMAX]; // 64-wide: column order, by the midpoint of the nonzero rows (ties: index)
+  __shared__ int2 prng_s[4];  // 64-wide: per panel of 16 compact positions, the rows [lo, hi) of its nonzeros
+  __shared__ int2 grng_s[4];  // 64-wide: the same per group of 16 positions of the column order
   __shared__ int cmp_s[2];    // [0] number of free weights m, [1] compact position of a released weight
   __shared__ double rt_s[2];  // slope g.d and ratio-test step of this iteration
   __shared__ int ctl[4];
@@ -325,6 +332,34 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
   int nent = 0;  // (thread 0) lower-triangle entries of the free-set Hessians built
 
   for (int i = tid; i < n; i += PN_THREADS) s[i] = srow[i];
+  if constexpr (KMAX == 64) {
+    // Columns ordered by where their nonzero rows sit: a panel of 16 neighbours
+    // then covers few bins, so the Hessian skips the steps where a panel
+    // holds only zeros and the gradient sweeps a group's rows only (rank
+    // sort, lane j ranks column j; then the rows of each group of 16)
+    if (wave == 0) {
+      const int2 bj = lane < k && band ? band[lane] : make_int2(0, n);
+      const int key = lane < k ? (band ? bj.x + bj.y : lane) : 0x7fffffff;
+      int rank = 0;
+#pragma unroll 8
+      for (int i = 0; i < 64; ++i) {
+        const int ki = __builtin_amdgcn_readlane(key, i);
+        rank += (ki < key || (ki == key && i < lane)) ? 1 : 0;
+      }
+      ord_s[rank] = lane;
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        int lo = (lane < k && (rank >> 4) == gq) ? bj.x : 0x7fffffff;
+        int hi = (lane < k && (rank >> 4) == gq) ? bj.y : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          lo = min(lo, __shfl_xor(lo, off, 64));
+          hi = max(hi, __shfl_xor(hi, off, 64));
+        }
+        if (lane == 0) grng_s[gq] = make_int2(lo, hi);
+      }
+    }
+  }
   for (int j = tid; j < KMAX; j += PN_THREADS) {
     const double wj = j < k ? (double)wrow[j] : 0.0;
     w[j] = wj > 0.0 ? wj : 0.0;
@@ -373,20 +408,34 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
       for (int cb0 = 0; cb0 < KMAX; cb0 += 64) {
         const int cb = cb0 + 16 * cg;
         if (bp < P && cb < k) {
-          double acc[16];  // columns cb + jj (those past k read row k - 1 and are dropped)
+          // positions cb + jj of the column order (64-wide: ord_s, else the
+          // index) and the 64-bin blocks holding the group's nonzero rows
+          int roff[16];
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) {
+            const int x = min(cb + jj, k - 1);
+            roff[jj] = __builtin_amdgcn_readfirstlane((KMAX == 64 ? ord_s[x] : x) * ld_dt * 4);
+          }
+          int b_lo = 0, b_hi = (n + 63) >> 6;
+          if constexpr (KMAX == 64) {
+            const int2 gr = grng_s[cg];
+            b_lo = __builtin_amdgcn_readfirstlane(gr.x >> 6);
+            b_hi = __builtin_amdgcn_readfirstlane(gr.y > gr.x ? (gr.y + 63) >> 6 : b_lo);
+          }
+          double acc[16];  // positions cb + jj (those past k read position k - 1 and are dropped)
 #pragma unroll
           for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-          for (int blk = 2 * bp; 64 * blk < n; blk += 2 * P) {  // two 64-bin blocks: 32 loads in flight
+          for (int blk = b_lo + 2 * bp; blk < b_hi; blk += 2 * P) {  // two 64-bin blocks: 32 loads in flight
             double li[2];
             float dv[2][16];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
               const int i = 64 * (blk + sb) + lane;
               const double lv = (double)l[min(i, n - 1)];  // unconditional (clamped) read, then masked
-              li[sb] = i < n ? lv : 0.0;
+              li[sb] = (i < n && blk + sb < b_hi) ? lv : 0.0;
               const int vo = min(i, n - 1) * 4;
 #pragma unroll
-              for (int jj = 0; jj < 16; ++jj) dv[sb][jj] = pn_ld(rs, vo, min(cb + jj, k - 1) * ld_dt * 4);
+              for (int jj = 0; jj < 16; ++jj) dv[sb][jj] = pn_ld(rs, vo, roff[jj]);
             }
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb)
@@ -405,8 +454,9 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           }
           acc[0] += __shfl_xor(acc[0], 2, 64);
           acc[0] += __shfl_xor(acc[0], 1, 64);
-          const int j = cb + (lane >> 2);
-          if ((lane & 3) == 0 && j < KMAX) {
+          const int xq = cb + (lane >> 2);
+          const int j = KMAX == 64 ? ord_s[xq & (KMAX - 1)] : xq;  // (positions >= k keep their index)
+          if ((lane & 3) == 0 && xq < KMAX) {
             if (P == 1) g[j] = j < k ? pn_pen_grad(p.pen, w[j], p.alpha, p.beta) + p.eps * acc[0] : 0.0;
             else gp[bp * KMAX + j] = acc[0];
           }
@@ -493,12 +543,24 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
       }
       if constexpr (KMAX == 64) {  // compact positions of the free weights (after the release)
         if (!stop) {
-          const bool fr = lane < k && (!act[lane] || lane == rel);
+          const int oj = ord_s[lane];  // the column at position lane of the order
+          const bool fr = lane < k && (!act[oj] || oj == rel);
           const unsigned long long fm = __ballot(fr);
           const int x = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-          if (fr) perm[x] = lane;
-          if (lane == rel) cmp_s[1] = x;
+          if (fr) perm[x] = oj;
+          if (fr && oj == rel) cmp_s[1] = x;
           if (lane == 0) cmp_s[0] = __popcll(fm);
+          const int2 bj = (fr && band) ? band[oj] : make_int2(0, n);
+#pragma unroll
+          for (int pp = 0; pp < 4; ++pp) {
+            int lo = (fr && (x >> 4) == pp) ? bj.x : 0x7fffffff, hi = (fr && (x >> 4) == pp) ? bj.y : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+              lo = min(lo, __shfl_xor(lo, off, 64));
+              hi = max(hi, __shfl_xor(hi, off, 64));
+            }
+            if (lane == 0) prng_s[pp] = make_int2(lo, hi);
+          }
         }
       }
       if (lane == 0) {
@@ -525,13 +587,12 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
       if constexpr (KMAX == 64 && sizeof(TH) == 8) {
         // FP64 matrix cores on the free weights only, in compact order: with m
         // free weights and NP = ceil(m / 16) panels, the NP (NP + 1) / 2 lower
-        // 16 x 16 blocks (p >= q).  Wave w takes the 4-bin steps w, w + 4, ...;
-        // in a step lane l supplies bin 4 st + l/16 and the column of the free
-        // weight at compact position 16 p + l%16 of every panel p, as the A
-        // operand (scaled by 1 / a_i) and as the B operand.
+        // 16 x 16 blocks (p >= q).  In a 4-bin step st lane l supplies bin
+        // 4 st + l/16 and the column of the free weight at compact position
+        // 16 p + l%16 of every panel p, as the A operand (scaled by 1 / a_i)
+        // and as the B operand.
         const int m = cmp_s[0];
         const int c16 = lane & 15, ks = lane >> 4;
-        const int nst = (n + 3) >> 2;
         const __amdgpu_buffer_rsrc_t rd = pn_rsrc(Dp, (long long)n * ld_d);
         int colb[4];  // byte offset of this lane's column in each panel (-1: padding)
 #pragma unroll
@@ -541,35 +602,53 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           f64x4 acc[NBLK];
 #pragma unroll
           for (int x = 0; x < NBLK; ++x) acc[x] = f64x4{0.0, 0.0, 0.0, 0.0};
-          // operands of step st into registers (zero past the last bin and in padding)
-          auto load_step = [&](int st, float (&v)[NP], double& sc) {
+          // Wave w takes the 4-bin steps w, w + 4, ... of the bins where some
+          // panel has nonzeros, four steps in flight; in a step a block's
+          // matrix-core operation is skipped when either panel holds only zeros
+          // there (a wave-uniform test: the skipped terms are exact zeros)
+          int lo_all = 0x7fffffff, hi_all = 0;
+#pragma unroll
+          for (int pp = 0; pp < NP; ++pp) {
+            lo_all = min(lo_all, prng_s[pp].x);
+            hi_all = max(hi_all, prng_s[pp].y);
+          }
+          const int st_lo = lo_all >> 2, st_hi = hi_all > lo_all ? (hi_all + 3) >> 2 : st_lo;
+          // Loads are unconditional at clamped addresses and their values are
+          // used as loaded (a select on them, or a load under a branch, makes
+          // the wait counters drain every step): a bin past the last or past
+          // the steps' range gets the scale 0, which zeroes its terms through
+          // the A operand, and padding positions (a clamped column) only reach
+          // rows and columns >= m, which the last pass below overwrites
+          auto load_step = [&](int st, float (&v)[NP], double& sc) __attribute__((always_inline)) {
             const int i = 4 * st + ks;
-            const bool in = i < n;  // (st < nst for every in-range bin)
             const int ro = min(i, n - 1) * ld_d * 4;
 #pragma unroll
-            for (int pp = 0; pp < NP; ++pp) v[pp] = (in && colb[pp] >= 0) ? pn_ld(rd, ro + max(colb[pp], 0), 0) : 0.f;
-            sc = in ? (double)ra[min(i, n - 1)] : 0.0;
+            for (int pp = 0; pp < NP; ++pp) v[pp] = pn_ld(rd, ro + max(colb[pp], 0), 0);
+            // (a product with a 0/1 mask, not a select, keeps the read unconditional)
+            sc = (double)ra[min(i, n - 1)] * (double)(st < st_hi && i < n);
           };
-          auto mfma_step = [&](const float (&v)[NP], double sc) {
+          auto mfma_step = [&](const float (&v)[NP], double sc) __attribute__((always_inline)) {
             double bq[NP], ap[NP];
+            bool nz[NP];  // the scaled panel has a nonzero entry (wave-uniform)
 #pragma unroll
             for (int pp = 0; pp < NP; ++pp) {
               bq[pp] = (double)v[pp];
               ap[pp] = bq[pp] * sc;
+              nz[pp] = __ballot(ap[pp] != 0.0) != 0ull;
             }
             int x = 0;
 #pragma unroll
             for (int pp = 0; pp < NP; ++pp)
 #pragma unroll
               for (int qq = 0; qq <= pp; ++qq, ++x)
-                acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
+                if (nz[pp] && nz[qq]) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
           };
-          // two steps of loads in flight behind the matrix-core work
           float v0[NP], v1[NP];
           double s0, s1;
-          load_step(wave, v0, s0);
-          load_step(wave + 4, v1, s1);
-          for (int st = wave; st < nst; st += 8) {
+          int st = st_lo + wave;
+          load_step(st, v0, s0);
+          load_step(st + 4, v1, s1);
+          for (; st < st_hi; st += 8) {
             mfma_step(v0, s0);
             load_step(st + 8, v0, s0);
             mfma_step(v1, s1);

@@ -223,7 +223,7 @@ void rg_iterate(otlm_ragged_s* r, bool chk, hipStream_t s) {
     a.mm_until = nullptr; a.it = 0; a.nit = r->nit; a.nfac = r->nfac;
     a.Lg = r->Lg; a.lg_stride = RG_LG_STRIDE; a.wH = r->wH; a.maskH = r->maskH; a.validH = r->validH;
     a.reuse_tol = OTLM_HESS_REUSE;
-    a.rg = r->pnspec; a.it_dev = r->it_dev; a.newton_after = r->newton_after;
+    a.rg = r->pnspec; a.band = r->band; a.it_dev = r->it_dev; a.newton_after = r->newton_after;
     a.flops = r->profile ? r->work + 2 : nullptr;
     a.pen = r->p.pen; a.max_newton = RG_NEWTON_MAX; a.eps = r->p.eps; a.alpha = r->p.alpha; a.beta = r->p.beta;
     a.gtol = RG_NEWTON_GTOL;

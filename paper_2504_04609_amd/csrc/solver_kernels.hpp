@@ -249,10 +249,11 @@ __global__ void build_kernel_f32(const double* __restrict__ C, int n, int np, do
 }
 
 // Dictionary copies: Dp [np, kp] (= D, zero padded), DTp [kp, np] (= D^T),
-// per-column constants colc[j] = {1/x_j, shift_j, gamma_j, log gamma_j}.
+// per-column constants colc[j] = {1/x_j, shift_j, gamma_j, log gamma_j} and
+// the rows holding its nonzero entries, band[j] = [lo, hi) ([0, 0) if none).
 __global__ void prep_dictionary(const float* __restrict__ D, int n, int k, int np, int kp, int pen, double eps,
                                 double alpha, double beta, float* __restrict__ Dp, float* __restrict__ DTp,
-                                float4* __restrict__ colc, int* __restrict__ bad) {
+                                float4* __restrict__ colc, int2* __restrict__ band, int* __restrict__ bad) {
   const int j = blockIdx.x;
   if (j >= kp) return;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
@@ -263,9 +264,17 @@ __global__ void prep_dictionary(const float* __restrict__ D, int n, int k, int n
   }
   if (threadIdx.x == 0) {
     float4 c = {0.f, 0.f, 1.f, 0.f};
+    int lo = n, hi = 0;
     if (j < k) {
       double x = 0.0;
-      for (int i = 0; i < n; ++i) x += (double)D[(size_t)i * k + j];
+      for (int i = 0; i < n; ++i) {
+        const float d = D[(size_t)i * k + j];
+        x += (double)d;
+        if (d != 0.f) {
+          lo = min(lo, i);
+          hi = i + 1;
+        }
+      }
       if (!(x > 0.0)) bad[0] = 1;
       double shift = 0.0, gam = 1.0;
       if (pen == PEN_L1) shift = alpha / (eps * x);
@@ -277,6 +286,7 @@ __global__ void prep_dictionary(const float* __restrict__ D, int n, int k, int n
       c = make_float4((float)(1.0 / x), (float)shift, (float)gam, (float)log(gam));
     }
     colc[j] = c;
+    band[j] = lo < hi ? make_int2(lo, hi) : make_int2(0, 0);
   }
 }
 
