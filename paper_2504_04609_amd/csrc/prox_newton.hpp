@@ -710,18 +710,20 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           for (int x = 0; x < NB; ++x)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[x][r] = 0.f;
+          // loads unconditional at clamped addresses and used as loaded (a bin
+          // past the last gets the scale 0, which zeroes its terms through the
+          // A operand): loads under a branch drain the wait counter every step
           auto load_step = [&](int st, float (&v)[4], float& sc) {
             const int i = 2 * st + kh;
-            const bool in = i < n;
             const int ro = (min(i, n - 1) * ld_d + l32) * 4;
 #pragma unroll
             for (int pp = 0; pp < 4; ++pp) {
               bool need = false;
 #pragma unroll
               for (int x = 0; x < NB; ++x) need = need || BP[W][x] == pp || BQ[W][x] == pp;
-              v[pp] = (need && in) ? pn_ld(rd, ro, 128 * pp) : 0.f;
+              v[pp] = need ? pn_ld(rd, ro, 128 * pp) : 0.f;
             }
-            sc = in ? (float)ra[min(i, n - 1)] : 0.f;
+            sc = (float)ra[min(i, n - 1)] * (float)(i < n);
           };
           auto mfma_step = [&](const float (&v)[4], float sc) {
 #pragma unroll

@@ -55,25 +55,32 @@ __device__ __forceinline__ float rg_wave_sum(float v) {
 // order (entries outside a column's band are exact zeros and add nothing).
 __device__ __forceinline__ void rg_dict_apply(const float* __restrict__ DTb, const int2* bnd, const float* w, int n,
                                               int k, float* a) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  // Loads are unconditional (a load under a per-lane branch drains the wait
+  // counter): a column whose band misses the wave's 64 bins is read at one bin
+  // just outside its band, the same address for every lane (an exact zero,
+  // one cache line), 16 loads in flight
+  const int lane = threadIdx.x & 63;
+  for (int i0 = threadIdx.x - lane; i0 < n; i0 += blockDim.x) {
+    const int ic = min(i0 + lane, n - 1);
     float acc = 0.f;
     int j = 0;
-    for (; j + 8 <= k; j += 8) {  // eight independent loads in flight
-      float d[8];
+    for (; j + 16 <= k; j += 16) {
+      float d[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 16; ++q) {
         const int2 bj = bnd[j + q];
-        d[q] = (i >= bj.x && i < bj.y) ? DTb[(size_t)(j + q) * n + i] : 0.f;
+        const int idx = (bj.x < i0 + 64 && bj.y > i0) ? ic : (bj.y <= i0 ? bj.y : bj.x - 1);
+        d[q] = DTb[(size_t)(j + q) * n + idx];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc = fmaf(d[q], w[j + q], acc);
+      for (int q = 0; q < 16; ++q) acc = fmaf(d[q], w[j + q], acc);
     }
     for (; j < k; ++j) {
       const int2 bj = bnd[j];
-      const float d = (i >= bj.x && i < bj.y) ? DTb[(size_t)j * n + i] : 0.f;
-      acc = fmaf(d, w[j], acc);
+      const int idx = (bj.x < i0 + 64 && bj.y > i0) ? ic : (bj.y <= i0 ? bj.y : bj.x - 1);
+      acc = fmaf(DTb[(size_t)j * n + idx], w[j], acc);
     }
-    a[i] = acc;
+    if (i0 + lane < n) a[i0 + lane] = acc;
   }
 }
 
@@ -270,16 +277,25 @@ __global__ __launch_bounds__(RG_WS_THREADS) void rg_weight_step(const RgSpec* __
     for (int j = wave; j < k; j += nwaves) {
       const int2 bj = bnd[j];
       const float* col = DTb + (size_t)j * n;
-      float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-      int i = bj.x + lane;
-      for (; i + 192 < bj.y; i += 256) {
-        acc0 = fmaf(col[i], r_s[i], acc0);
-        acc1 = fmaf(col[i + 64], r_s[i + 64], acc1);
-        acc2 = fmaf(col[i + 128], r_s[i + 128], acc2);
-        acc3 = fmaf(col[i + 192], r_s[i + 192], acc3);
+      // the band in 64-bin chunks, 8 unconditional loads in flight (clamped
+      // into the column; bins past the band read exact zeros, bins past the
+      // last get r = 0)
+      float acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+      for (int i0 = bj.x; i0 < bj.y; i0 += 512) {
+        float d[8], rv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = i0 + 64 * q + lane;
+          const int ic = min(i, n - 1);
+          d[q] = col[ic];
+          rv[q] = r_s[ic] * (float)(i < n);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = fmaf(d[q], rv[q], acc[q]);
       }
-      for (; i < bj.y; i += 64) acc0 = fmaf(col[i], r_s[i], acc0);
-      const float c = rg_wave_sum((acc0 + acc1) + (acc2 + acc3));
+      const float c = rg_wave_sum(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
       if (lane == 0) {
         const float4 cj = cc[j];
         const float wold = w[j];
