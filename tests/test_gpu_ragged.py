@@ -15,6 +15,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle as orc
+from dictionaries import gapped_dictionary
 from paper_2504_04609_amd import otlm, synth
 
 pytestmark = pytest.mark.gpu
@@ -254,3 +255,35 @@ def test_newton_graph_replay_equals_eager(small):
     _, b = small.solve(p, use_graph=False, tile=0, newton_after=3)
     for key in ("W", "logV", "iters", "status"):
         np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+
+
+def test_gapped_dictionaries_reach_oracle():
+    """Own dictionaries with interior gaps, dense columns and narrow columns near
+    the grid's ends (shuffled, no two alike), widths on both Newton kernels (40,
+    64; 100 on the 128-wide one): the banded MM steps, the column order of the
+    64-wide prox and the skipped Hessian block-steps must still reach the oracle
+    (bar 1e-5)."""
+    wl = SMALL
+    n = 200
+    ks = [40, 64, 100, 64]
+    Ds = [gapped_dictionary(n, k, 40 + i) for i, k in enumerate(ks)]
+    rng = np.random.default_rng(41)
+    Ys = [(rng.exponential(1.0, k) @ D.T.astype(np.float64) + np.abs(rng.normal(0.0, 1e-3, n))).astype(np.float32)
+          for D, k in zip(Ds, ks)]
+    C = wl.cost(n)
+    kern = otlm.GibbsKernel(gpu(C, torch.float64), wl.eps)
+    kernel_of = np.zeros(len(ks), dtype=np.int32)
+    kdim = np.array(ks, dtype=np.int32)
+    plan = otlm.RaggedPlan([kern], kernel_of, kdim, params(wl), newton_after=3)
+    out = plan.solve(gpu(np.concatenate([D.ravel() for D in Ds])), gpu(np.concatenate(Ys)))
+    torch.cuda.synchronize()
+    assert (out["status"].cpu().numpy() == otlm.STATUS_CONVERGED).all()
+    W = out["W"].cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(ks)])
+    K = orc.gibbs_kernel(C, wl.eps)
+    for b, (D, y) in enumerate(zip(Ds, Ys)):
+        ref = orc.solve(K, D.astype(np.float64), y.astype(np.float64)[None], fit=wl.fit, pen=wl.pen, eps=wl.eps,
+                        lam=wl.lam, lam2=wl.lam2, alpha=wl.alpha, beta=wl.beta, max_iter=2000, tol=1e-12,
+                        mode="exact")["W"][0]
+        assert rel_err(W[off[b]:off[b + 1]], ref) <= 1e-5, b
+

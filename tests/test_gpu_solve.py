@@ -17,6 +17,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle as orc
+from dictionaries import gapped_dictionary
 from paper_2504_04609_amd import otlm, synth
 
 pytestmark = pytest.mark.gpu
@@ -272,6 +273,28 @@ def test_exact_prox_every_dictionary_width(k, pen, alpha):
     Bar: 1e-5 on every spectrum."""
     wl = synth.Workload(f"width{k}", n=200, k=k, B=6, eps=0.01, fit="kl", pen=pen, lam=1.0, alpha=alpha, seed=21)
     D32, Y32, C = setup(wl, range(wl.B))
+    ref = oracle_solve(C, D32, Y32, wl, max_iter=600, tol=1e-11, mode="exact")
+    assert ref["converged"].all()
+    _, res = gpu_solve(C, D32, Y32, wl, tol=1e-9, bulk_tol=1e-4, max_iter=400, check_every=5, wstep="exact",
+                       inner_max=8, refine="fp64", refine_sweeps=300)
+    assert np.all(res["status"] == otlm.STATUS_CONVERGED), res["status"]
+    err = rel_err(res["W"], ref["W"])
+    assert err.max() <= 1e-5, err
+
+
+@pytest.mark.parametrize("k,pen,alpha", [(40, "l2sq", 1e-3), (64, "l2sq", 1e-3), (64, "l1", 1e-2)])
+def test_exact_prox_gapped_dictionary(k, pen, alpha):
+    """The Newton prox orders the free weights by where their columns' nonzero
+    rows sit and skips the Hessian's all-zero block-steps (and the gradient's
+    empty bin blocks); columns with interior gaps, dense columns and columns at
+    the grid's ends, shuffled, must still reach the oracle (FP64 refinement,
+    bar 1e-5 on every spectrum)."""
+    wl = synth.Workload(f"gapped{k}", n=200, k=k, B=6, eps=0.01, fit="kl", pen=pen, lam=1.0, alpha=alpha, seed=23)
+    D32 = gapped_dictionary(wl.n, k, 31)
+    rng = np.random.default_rng(32)
+    W = rng.exponential(1.0, (wl.B, k))
+    Y32 = as_f32(W @ D32.T.astype(np.float64) + np.abs(rng.normal(0.0, 1e-3, (wl.B, wl.n))))
+    C = wl.cost()
     ref = oracle_solve(C, D32, Y32, wl, max_iter=600, tol=1e-11, mode="exact")
     assert ref["converged"].all()
     _, res = gpu_solve(C, D32, Y32, wl, tol=1e-9, bulk_tol=1e-4, max_iter=400, check_every=5, wstep="exact",
