@@ -643,16 +643,24 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
               for (int qq = 0; qq <= pp; ++qq, ++x)
                 if (nz[pp] && nz[qq]) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[pp], bq[qq], acc[x], 0, 0, 0);
           };
-          float v0[NP], v1[NP];
-          double s0, s1;
-          int st = st_lo + wave;
+          // double buffer of two steps each: each half issues the other
+          // buffer's loads first, so the buffer consumed next is the oldest one
+          // in flight on every path into the loop (a loop whose first use is
+          // the newest load makes the compiler drain the wait counter there)
+          float v0[NP], v1[NP], v2[NP], v3[NP];
+          double s0, s1, s2, s3;
+          int st = st_lo + __builtin_amdgcn_readfirstlane(wave);
           load_step(st, v0, s0);
           load_step(st + 4, v1, s1);
-          for (; st < st_hi; st += 8) {
+          for (; st < st_hi; st += 16) {
+            load_step(st + 8, v2, s2);
+            load_step(st + 12, v3, s3);
             mfma_step(v0, s0);
-            load_step(st + 8, v0, s0);
             mfma_step(v1, s1);
-            load_step(st + 12, v1, s1);
+            load_step(st + 16, v0, s0);
+            load_step(st + 20, v1, s1);
+            mfma_step(v2, s2);
+            mfma_step(v3, s3);
           }
           // sum the four waves' partial blocks into H in wave order (lane l,
           // register r holds block row l/16 + 4 r, block column l%16); the last
