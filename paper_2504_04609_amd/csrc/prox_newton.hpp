@@ -419,8 +419,8 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
           int b_lo = 0, b_hi = (n + 63) >> 6;
           if constexpr (KMAX == 64) {
             const int2 gr = grng_s[cg];
-            b_lo = __builtin_amdgcn_readfirstlane(gr.x >> 6);
-            b_hi = __builtin_amdgcn_readfirstlane(gr.y > gr.x ? (gr.y + 63) >> 6 : b_lo);
+            b_lo = __builtin_amdgcn_readfirstlane(gr.y > gr.x ? gr.x >> 6 : 0);
+            b_hi = __builtin_amdgcn_readfirstlane(gr.y > gr.x ? (gr.y + 63) >> 6 : 0);
           }
           double acc[16];  // positions cb + jj (those past k read position k - 1 and are dropped)
 #pragma unroll
@@ -612,7 +612,9 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
             lo_all = min(lo_all, prng_s[pp].x);
             hi_all = max(hi_all, prng_s[pp].y);
           }
-          const int st_lo = lo_all >> 2, st_hi = hi_all > lo_all ? (hi_all + 3) >> 2 : st_lo;
+          // (no nonzero rows: no steps, and the prologue's loads stay at bin 0..)
+          const bool rows = hi_all > lo_all;
+          const int st_lo = rows ? lo_all >> 2 : 0, st_hi = rows ? (hi_all + 3) >> 2 : 0;
           // Loads are unconditional at clamped addresses and their values are
           // used as loaded (a select on them, or a load under a branch, makes
           // the wait counters drain every step): a bin past the last or past
