@@ -304,6 +304,21 @@ def test_exact_prox_gapped_dictionary(k, pen, alpha):
     assert err.max() <= 1e-5, err
 
 
+def test_exact_prox_column_order_invariance():
+    """Permuting the dictionary's columns permutes the weights: the prox orders
+    its free weights by where the columns' nonzero rows sit (ties by index), so
+    the two solves differ only in rounding (FP64 refinement to tol 1e-9)."""
+    wl = synth.Workload("perm48", n=200, k=48, B=6, eps=0.01, fit="kl", pen="l1", lam=1.0, alpha=1e-2, seed=25)
+    D32, Y32, C = setup(wl, range(wl.B))
+    perm = np.random.default_rng(26).permutation(wl.k)
+    kw = dict(tol=1e-9, bulk_tol=1e-4, max_iter=400, check_every=5, wstep="exact", inner_max=8, refine="fp64",
+              refine_sweeps=300)
+    _, a = gpu_solve(C, D32, Y32, wl, **kw)
+    _, b = gpu_solve(C, np.ascontiguousarray(D32[:, perm]), Y32, wl, **kw)
+    assert (a["status"] == otlm.STATUS_CONVERGED).all() and (b["status"] == otlm.STATUS_CONVERGED).all()
+    assert rel_err(b["W"], a["W"][:, perm]).max() <= 2e-6
+
+
 def test_exact_prox_rejects_large_dictionaries():
     n, k = 128, 80
     dic = synth.make_dictionary(n, k, 4)
