@@ -68,6 +68,14 @@ PMC_TRAFFIC = os.path.join(ROOT, "profiles", "pmc_traffic_prox_newton_fp32_warm_
 PMC_SOURCES = [os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "prox_newton.hpp"),
                os.path.join(ROOT, "paper_2504_04609_amd", "csrc", "otlm.hip"),
                os.path.abspath(__file__)]
+# the same for the ragged row's kernels (MM weight step; Newton prox, both widths)
+PMC_TRAFFIC_RAGGED = {
+    "per-spectrum weight step": os.path.join(ROOT, "profiles", "pmc_traffic_rg_weight_step_ragged_8192.txt"),
+    "prox_newton_kernel<float, float, float> (64- and 128-wide launches)":
+        os.path.join(ROOT, "profiles", "pmc_traffic_prox_newton_ragged_8192.txt")}
+PMC_SOURCES_RAGGED = [os.path.join(ROOT, "paper_2504_04609_amd", "csrc", f)
+                      for f in ("prox_newton.hpp", "otlm.hip", "ragged.hpp", "ragged_kernels.hpp")] + \
+                     [os.path.abspath(__file__)]
 COPY_BYTES = 256 << 20
 BASELINE_ARM = "fp32_64_cold"
 # warm-start probe: l1 relative weight change over the first test interval. On the
@@ -115,24 +123,24 @@ def arm_params(name, wl, otlm):
     raise ValueError(name)
 
 
-def sources_digest():
+def sources_digest(paths=None):
     """sha256 over the files that decide the measured kernel's launches."""
     import hashlib
     h = hashlib.sha256()
-    for path in PMC_SOURCES:
+    for path in (PMC_SOURCES if paths is None else paths):
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, path=None, sources=None):
     """Bytes per launch of `kernel` from the committed counter summary, or None
     when there is none or the kernel, the engine or the benchmark settings have
     changed since it was taken."""
     try:
-        with open(PMC_TRAFFIC) as f:
+        with open(PMC_TRAFFIC if path is None else path) as f:
             kv = dict(ln.split(":", 1) for ln in f if ":" in ln and not ln.startswith("#"))
-        digest = sources_digest()
+        digest = sources_digest(sources)
     except OSError:
         return None
     kv = {a.strip(): b.strip() for a, b in kv.items()}
@@ -368,6 +376,8 @@ def ragged_row(args, otlm, synth, torch):
     entries = (prod, wstep, newton)
     for e in entries:
         e["frac"] = e["achieved"] / e["peak"]
+        if e["kernel"] in PMC_TRAFFIC_RAGGED:
+            e["traffic"] = pmc_traffic(e["kernel"], PMC_TRAFFIC_RAGGED[e["kernel"]], PMC_SOURCES_RAGGED)
     dominant = max(entries, key=lambda e: e["ms_per_launch"] * e["launches"])
     row = {"workload": wl.name, "B": wl.B, "n": list(ns), "k": sorted(set(int(x) for x in kdim)),
            "datafit": "l2+tv", "lambda": wl.lam, "lambda2": wl.lam2, "penalty": "l2sq", "alpha": wl.alpha,
