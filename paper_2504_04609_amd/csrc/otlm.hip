@@ -570,7 +570,9 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
     EpiStore e{ws.A, (int)np, (int)n, false};
     gemm(64, 128, g, e, s);
   }
-  const int bm_k = B >= 4096 ? 128 : 64, bn_k = 128;
+  // 64 x 128 tiles: at B = 4096, n = 1024 the 512 tiles put two workgroups on
+  // every CU (128 x 128 tiles give one, with nothing to cover its latencies)
+  const int bm_k = 64, bn_k = 128;
   const int nts = (int)((np + bn_k - 1) / bn_k);
   const int bn_w = kp >= 128 ? 128 : 64;
   ProxConsts pc;
@@ -638,7 +640,7 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       } else {
         ProfScope ps(k, PROF_KV32, s);
         GemmArgs g{ws.V, (int)np, k->K, (int)np, Ma, (int)np, (int)np};
-        gemm(2 * Ma <= M ? 64 : bm_k, bn_k, g, e, s, arows);
+        gemm(bm_k, bn_k, g, e, s, arows);
       }
     }
     if (exact) {  // weight prox solved by active-set Newton (spectra past their MM warm-up)
