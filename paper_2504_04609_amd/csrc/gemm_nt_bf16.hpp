@@ -30,9 +30,12 @@ struct GemmArgsBf16 {
   int M, N, Kd;
 };
 
-template <class Epi>
+// BM rows per tile (128, or 64: FM = BM / 64 fragments of 32 rows per wave),
+// BN = 128 columns.
+template <class Epi, int BM = GB_BM>
 __global__ __launch_bounds__(256) void gemm_nt_bf16(GemmArgsBf16 g, Epi epi) {
-  constexpr int BM = GB_BM, BN = GB_BN, BK = GB_BK, LD = GB_LD;
+  static_assert(BM == 128 || BM == 64, "tile rows");
+  constexpr int BN = GB_BN, BK = GB_BK, LD = GB_LD, FM = BM / 64;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN * LD];
   __shared__ float red_s[2][BM][2];
@@ -41,14 +44,16 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16(GemmArgsBf16 g, Epi epi) {
   const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
 
-  // a 128 x 32 tile is 512 chunks of 8 elements: two per thread per operand
-  u16x8 ra[2], rb[2];
+  // a 128 x 32 tile is 512 chunks of 8 elements: two per thread (one for a
+  // 64-row A tile)
+  u16x8 ra[FM], rb[2];
   auto gload = [&](int kt) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 8;
       const int gm = m0 + r, gn = n0 + r;
-      ra[q] = gm < g.M ? *reinterpret_cast<const u16x8*>(g.A + (size_t)gm * g.lda + kt * BK + c) : u16x8{};
+      if (q < FM)
+        ra[q] = gm < g.M ? *reinterpret_cast<const u16x8*>(g.A + (size_t)gm * g.lda + kt * BK + c) : u16x8{};
       rb[q] = gn < g.N ? *reinterpret_cast<const u16x8*>(g.Bt + (size_t)gn * g.ldb + kt * BK + c) : u16x8{};
     }
   };
@@ -56,14 +61,14 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16(GemmArgsBf16 g, Epi epi) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + q * 256, r = idx >> 2, c = (idx & 3) * 8;
-      *reinterpret_cast<u16x8*>(&As[buf][r * LD + c]) = ra[q];
+      if (q < FM) *reinterpret_cast<u16x8*>(&As[buf][r * LD + c]) = ra[q];
       *reinterpret_cast<u16x8*>(&Bs[buf][r * LD + c]) = rb[q];
     }
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[FM][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -78,16 +83,17 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16(GemmArgsBf16 g, Epi epi) {
     if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[FM], b[2];
 #pragma unroll
-      for (int f = 0; f < 2; ++f) {
+      for (int f = 0; f < FM; ++f)
         a[f] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(
-                                              &As[cur][(wm * 64 + f * 32 + l32) * LD + kk * 16 + h * 8]));
+                                              &As[cur][(wm * (BM / 2) + f * 32 + l32) * LD + kk * 16 + h * 8]));
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
         b[f] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(
                                               &Bs[cur][(wn * 64 + f * 32 + l32) * LD + kk * 16 + h * 8]));
-      }
 #pragma unroll
-      for (int fm = 0; fm < 2; ++fm)
+      for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int fn = 0; fn < 2; ++fn)
           acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
@@ -99,10 +105,10 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16(GemmArgsBf16 g, Epi epi) {
   // 32x32 accumulator layout: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4,
   // column l%32 of its fragment.
 #pragma unroll
-  for (int fm = 0; fm < 2; ++fm) {
+  for (int fm = 0; fm < FM; ++fm) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = wm * 64 + fm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+      const int row = wm * (BM / 2) + fm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
       const int m = m0 + row;
       float red[2] = {0.f, 0.f};
       if (m < g.M) {

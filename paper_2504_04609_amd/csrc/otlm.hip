@@ -621,10 +621,9 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
   int mm_until_max = (exact && !p->warm) ? OTLM_MM_WARMUP : 0;
   // Rows of the FP32 / FP64 kernel products: all spectra at the start of a
   // phase, then the active ones listed after each convergence test (spectra
-  // that stopped are frozen, so their rows need no products).  A full product
-  // fills the chip with one wave of 128-row tiles, so once the active rows
-  // fall to half the batch the products take 64-row tiles (and K^T u 64 x 64)
-  // to keep the tile count up.
+  // that stopped are frozen, so their rows need no products).  The products
+  // take 64-row tiles, and K^T u 64 x 64 ones once the active rows fall to half
+  // the batch, to keep the tile count up.
   int Ma = M;
   const int* arows = nullptr;
   // One FP32 iteration (bulk phase or FP32 refinement); `it` counts from 1 over the whole solve.
@@ -635,8 +634,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       if (bf16) {
         ProfScope ps(k, PROF_KVBF, s);
         GemmArgsBf16 g{ws.Vbf, (int)np, k->Kbf, (int)np, M, (int)np, (int)np};
-        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + GB_BM - 1) / GB_BM));
-        hipLaunchKernelGGL(gemm_nt_bf16<EpiSrc>, grid, dim3(256), 0, s, g, e);
+        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + 63) / 64));
+        hipLaunchKernelGGL((gemm_nt_bf16<EpiSrc, 64>), grid, dim3(256), 0, s, g, e);
       } else {
         ProfScope ps(k, PROF_KV32, s);
         GemmArgs g{ws.V, (int)np, k->K, (int)np, Ma, (int)np, (int)np};
@@ -667,8 +666,8 @@ int otlm_solve_batch(otlm_kernel k, const float* D, int64_t kdim, const float* Y
       if (bf16) {
         ProfScope ps(k, PROF_KTUBF, s);
         GemmArgsBf16 g{ws.Ubf, (int)np, k->KTbf, (int)np, M, (int)np, (int)np};
-        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + GB_BM - 1) / GB_BM));
-        hipLaunchKernelGGL(gemm_nt_bf16<EpiProx>, grid, dim3(256), 0, s, g, e);
+        dim3 grid((unsigned)((np + GB_BN - 1) / GB_BN), (unsigned)((B + 63) / 64));
+        hipLaunchKernelGGL((gemm_nt_bf16<EpiProx, 64>), grid, dim3(256), 0, s, g, e);
       } else {
         ProfScope ps(k, PROF_KTU32, s);
         GemmArgs g{ws.U, (int)np, k->KT, (int)np, Ma, (int)np, (int)np};
