@@ -612,7 +612,7 @@ __global__ __launch_bounds__(PN_THREADS, 2) void prox_newton_kernel(ProxNewtonAr
             lo_all = min(lo_all, prng_s[pp].x);
             hi_all = max(hi_all, prng_s[pp].y);
           }
-          // (no nonzero rows: no steps, and the prologue's loads stay at bin 0..)
+          // (no nonzero rows: no steps; the prologue still loads, at clamped bins)
           const bool rows = hi_all > lo_all;
           const int st_lo = rows ? lo_all >> 2 : 0, st_hi = rows ? (hi_all + 3) >> 2 : 0;
           // Loads are unconditional at clamped addresses and their values are
